@@ -1,0 +1,130 @@
+"""CPU oracle for leveled-DAG diagram summation -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library and the library
+never calls it.
+
+  level_sweep.c  plain FP64 level-by-level evaluator (C, OpenMP over samples)
+  path_sum.py    the definition itself: exact rational sum over all paths
+
+Functions here only marshal numpy arrays into the C evaluator.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "level_sweep.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MODES = {"value": 0, "abs": 1, "square": 2}
+
+
+def _src_hash(src_path: str = _SRC) -> str:
+    with open(src_path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def build(out: str = _LIB, src: str = _SRC, defines: tuple = ()) -> str:
+    """Compile level_sweep.c with gcc (FP64, no contraction, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", f'-DORACLE_SRC_HASH="{_src_hash(src)}"', *defines,
+           "-o", out, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def _bind(lib):
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_src_hash.restype = ctypes.c_char_p
+    lib.oracle_check.restype = ctypes.c_int
+    lib.oracle_check.argtypes = [i32, p, p, p, p, p, p, p]
+    lib.oracle_sweep.restype = ctypes.c_int
+    lib.oracle_sweep.argtypes = [i32, p, p, p, p, p, p, p, p, i64, i32, i32, p, p]
+    return lib
+
+
+def load(path: str = _LIB, rebuild_if_stale: bool = True):
+    """Load the compiled oracle (building it when missing or out of date)."""
+    global _lib
+    if path == _LIB and _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        if not rebuild_if_stale:
+            raise FileNotFoundError(path)
+        build(path)
+    lib = _bind(ctypes.CDLL(path))
+    if path == _LIB:
+        if lib.oracle_src_hash().decode() != _src_hash() and rebuild_if_stale:
+            build(path)
+            lib = _bind(ctypes.CDLL(path))
+        _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _arrays(g):
+    return dict(
+        widths=np.ascontiguousarray(g.widths, dtype=np.int64),
+        epl=np.ascontiguousarray(g.epl, dtype=np.int64),
+        src=np.ascontiguousarray(g.src, dtype=np.int32),
+        dst=np.ascontiguousarray(g.dst, dtype=np.int32),
+        a=np.ascontiguousarray(g.a, dtype=np.float64),
+        b=np.ascontiguousarray(g.b, dtype=np.float64),
+        k=np.ascontiguousarray(g.k, dtype=np.float64).reshape(-1),
+    )
+
+
+def check(g, lib=None) -> bool:
+    lib = lib or load()
+    A = _arrays(g)
+    return lib.oracle_check(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "a", "b", "k")]) == 0
+
+
+def sweep(g, x, mode: str = "value", threads: int = 0, lib=None, return_threads: bool = False):
+    """Evaluate the final-node value (or its |w| / w^2 norm sweeps) for x[3,S]."""
+    lib = lib or load()
+    A = _arrays(g)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim != 2 or x.shape[0] != 3:
+        raise ValueError("x must be float64[3, S]")
+    S = x.shape[1]
+    out = np.empty(S, dtype=np.float64)
+    used = ctypes.c_int32(0)
+    rc = lib.oracle_sweep(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "a", "b", "k")],
+                          _ptr(x), S, MODES[mode], int(threads), _ptr(out), ctypes.byref(used))
+    if rc != 0:
+        raise ValueError(f"oracle_sweep failed with code {rc}")
+    return (out, used.value) if return_threads else out
+
+
+def evaluate(g, x, threads: int = 0, lib=None):
+    """(V, A, Q): value, 1-norm and squared 2-norm of the path terms per sample."""
+    return (sweep(g, x, "value", threads, lib), sweep(g, x, "abs", threads, lib),
+            sweep(g, x, "square", threads, lib))
+
+
+def scaled_error(y, r, Q):
+    """Per-sample error |y - r| / max(|r|, sqrt(Q)).
+
+    Plain relative error is unbounded near the sign changes of V(x) for any
+    evaluator; sqrt(Q) (the 2-norm of the individual path terms) is the natural
+    scale of the sum there.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    den = np.maximum(np.abs(r), np.sqrt(np.asarray(Q, dtype=np.float64)))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.abs(y - r) / den
+    e[(den == 0) & (y == r)] = 0.0
+    return e
