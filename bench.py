@@ -1,0 +1,230 @@
+"""Benchmark: edge-sample updates/s of the leveled-DAG level sweep on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload mid] [--precision fp64]
+
+One step = one full evaluation (every level, the final-node reduction, and for
+the rescaled FP32 path the exponent bookkeeping) of the workload's graph for
+all S samples, with the graph, the samples and the workspace already resident
+in HBM.  Prints one JSON line.  The CPU-baseline leg times the plain FP64
+oracle on the host cores; its outputs are also the reference for the reported
+error of the GPU results.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edge-sample updates/s (FP64 vs FP32) at stated rel err; p50/p99 request latency"
+UNIT = "edge-sample updates/s"
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32r": 157.3, "fp32": 157.3}
+# algorithmic flops per edge-sample of the fused factor + accumulate:
+# 3 sub, |.|^2 = 1 mul + 2 fma (5), 1 + b r^2 = fma (2), divide (1), acc fma (2)
+FLOPS_PER_EDGE_SAMPLE = 13
+TOL = {"fp64": 1e-12, "fp32r": 1e-5, "fp32": 1e-5}
+DTYPE = {"fp64": "f64", "fp32r": "f32", "fp32": "f32"}
+WORKLOAD_TEXT = {
+    "tiny": "tiny: L=4, widths [1,3,4,3,1], in-degree 2, S=1024, x~U[-1,1]^3",
+    "mid": "mid: L=12, interior width 256, in-degree 4, S=65536, x~N(0,I3)",
+    "precision": "precision: L=24, interior width 4096, in-degree 8, S=4096, x~U[-1,1]^3, b~U[0.1,4]",
+    "large": "large: L=32, interior width 65536, in-degree 6, S=1024, x~N(0,I3), b~U[0.1,4]",
+}
+
+
+def level_bytes(g, S_pad: int, precision: str) -> list:
+    """Algorithmic bytes of each interior-level launch: read the previous level's
+    rows once, write this level's rows once, read the edge records and row
+    pointers once, read x once (S samples, 3 x float64)."""
+    B = 8 if precision == "fp64" else 4
+    rec = 48 if precision == "fp64" else 32
+    out = []
+    for l in range(1, g.L):
+        w_prev = 0 if l == 1 else int(g.widths[l - 1])  # level 1 reads the root's constant 1
+        out.append((w_prev + int(g.widths[l])) * S_pad * B + int(g.epl[l - 1]) * rec
+                   + 4 * (int(g.widths[l]) + 1) + 24 * S_pad)
+    return out
+
+
+def cpu_info() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            m = re.search(r"model name\s*:\s*(.*)", f.read())
+            return m.group(1).strip() if m else platform.processor()
+    except OSError:
+        return platform.processor()
+
+
+def cpu_baseline_leg(g, x, idx_ref, target_s: float = 12.0):
+    """Time the FP64 oracle on the host cores; also return its values on idx_ref."""
+    import oracle
+
+    S = x.shape[1]
+    E = g.n_edges
+    # calibrate on a small slice, then time a bounded sample of ~target_s seconds
+    cal = min(S, 512)
+    t0 = time.perf_counter()
+    oracle.sweep(g, np.ascontiguousarray(x[:, :cal]))
+    dt = max(time.perf_counter() - t0, 1e-6)
+    n = int(min(S, max(cal, cal * target_s / dt)))
+    xs = np.ascontiguousarray(x[:, :n])
+    t0 = time.perf_counter()
+    _, used = oracle.sweep(g, xs, return_threads=True)
+    t = time.perf_counter() - t0
+    xr = np.ascontiguousarray(x[:, idx_ref])
+    V = oracle.sweep(g, xr, "value")
+    Q = oracle.sweep(g, xr, "square")
+    base = {"value": E * n / t, "unit": UNIT, "cores": int(used), "kind": "oracle",
+            "sample": f"first {n} of {S} samples of the same graph ({E} edges), FP64 level sweep, "
+                      f"{t:.1f} s on {cpu_info()}"}
+    return base, V, Q
+
+
+def error_stats(y, V, Q, precision):
+    import oracle
+
+    scaled = oracle.scaled_error(y, V, Q)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        plain = np.abs(y - V) / np.abs(V)
+    plain = plain[np.isfinite(plain)]
+    return {"scaled_max": float(scaled.max()), "tol": TOL[precision],
+            "pass": bool(np.all(scaled <= TOL[precision])),
+            "plain_rel_p50": float(np.percentile(plain, 50)), "plain_rel_p99": float(np.percentile(plain, 99)),
+            "plain_rel_max": float(plain.max()), "samples_checked": int(len(y)),
+            "definition": "|y-r|/max(|r|,sqrt(Q)), r = FP64 oracle, Q = sum over paths of prod w^2"}
+
+
+def run_timed(P, G, xd, precision, steps, warmup):
+    import torch
+
+    S = xd.shape[1]
+    ws = torch.empty(G.workspace_bytes(S, precision), dtype=torch.uint8, device=xd.device)
+    out = torch.empty(S, dtype=torch.float64, device=xd.device)
+    for _ in range(warmup):
+        G.evaluate(xd, precision, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    for k in ("level", "fused", "final_partial", "final_combine", "fill"):
+        P.timing_read(k)
+    P.timing_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        G.evaluate(xd, precision, out=out, workspace=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    P.timing_enable(False)
+    ms = start.elapsed_time(stop) / steps
+    kern = {}
+    for k in ("level", "fused", "final_partial", "final_combine", "fill"):
+        t, n = P.timing_read(k)
+        if n:
+            kern[k] = {"total_ms": t, "launches": n, "avg_us": 1000.0 * t / n}
+    return ms, kern, out
+
+
+def roofline(g, S_pad, precision, kern, steps):
+    """Roofline of the dominant kernel class, from its live HIP-event timings."""
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    if dom == "level":
+        per_launch = level_bytes(g, S_pad, precision)
+        n_launch = len(per_launch)
+        bytes_step = float(sum(per_launch))
+        es_step = float(sum(int(g.epl[l - 1]) for l in range(1, g.L))) * S_pad
+        t_step = kern[dom]["total_ms"] / 1000.0 / steps
+        hbm = bytes_step / t_step / 1e9
+        alu = es_step * FLOPS_PER_EDGE_SAMPLE / t_step / 1e12
+        f_h, f_a = hbm / HBM_PEAK_GBS, alu / VALU_PEAK_TFLOPS[precision]
+        if f_h >= f_a:
+            r = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": f_h}
+        else:
+            r = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                 "frac": f_a}
+        r.update({"kernel": "level_gather_kernel", "avg_launch_us": kern[dom]["avg_us"],
+                  "launches_per_step": n_launch, "algorithmic_bytes_per_launch": bytes_step / n_launch,
+                  "other_term": ({"alu_tflops": alu, "alu_frac": f_a} if r["bound"] == "hbm"
+                                 else {"hbm_gbs": hbm, "hbm_frac": f_h})})
+    else:
+        r = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "kernel": dom}
+    r["traffic"] = None
+    return r
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mid", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r", "fp32"])
+    ap.add_argument("--variants", default="fp32r", help="comma list of extra precisions to time ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the path shards over samples with no "
+                                   "per-level exchange (see the design notes), but no multi-GPU run is provided",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2501_00675_amd as P
+    from workloads import make_config
+
+    g, x = make_config(args.workload)
+    S = x.shape[1]
+    E = g.n_edges
+    G = P.Graph.from_leveled(g)
+    xd = torch.from_numpy(x).to("cuda:0")
+    S_pad = (S + 255) // 256 * 256
+
+    print(f"# bench {args.workload} S={S} E={E} precision={args.precision} steps={args.steps}", file=sys.stderr,
+          flush=True)
+    ms, kern, out = run_timed(P, G, xd, args.precision, args.steps, args.warmup)
+    y = out.cpu().numpy()
+    value = E * S / (ms / 1000.0)
+    result = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[args.precision], "data": "synthetic (seeded generator; stands in for the paper's CoS graphs)",
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "L": g.L, "edges": E, "nodes": g.n_nodes, "S": S,
+                   "precision": args.precision, "seed": g.meta.get("seed")},
+        "kernels": kern,
+        "roofline": roofline(g, S_pad, args.precision, kern, args.steps),
+    }
+    variants = {}
+    for pv in [v for v in args.variants.split(",") if v and v != args.precision]:
+        print(f"# variant {pv}", file=sys.stderr, flush=True)
+        msv, kv, outv = run_timed(P, G, xd, pv, args.steps, args.warmup)
+        variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "kernels": kv,
+                        "roofline": roofline(g, S_pad, pv, kv, args.steps), "_y": outv.cpu().numpy()}
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        idx = np.unique(np.concatenate([[0, S - 1], np.random.default_rng(0).choice(S, min(S, 1024) - 2,
+                                                                                     replace=False)]))
+        base, V, Q = cpu_baseline_leg(g, x, idx, args.cpu_seconds)
+        result["cpu_baseline"] = base
+        result["accuracy"] = error_stats(y[idx], V, Q, args.precision)
+        for pv, d in variants.items():
+            d["accuracy"] = error_stats(d["_y"][idx], V, Q, pv)
+    else:
+        result["cpu_baseline"] = None
+    for d in variants.values():
+        d.pop("_y", None)
+    result["variants"] = variants
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * cos.h -- C ABI of the leveled-DAG diagram-summation library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The operation (paper Sec. II.B, caption of Fig. combinedgraphflat): a
+ * directed graph whose nodes sit on levels l = 0..L, with a single root on
+ * level 0 and a single final node on level L, and edges only from level l-1 to
+ * level l.  The root holds 1; each edge multiplies the value at its source by
+ * its edge factor and adds the product into its destination; the final node
+ * then holds the sum, over every root-to-final path, of the product of the
+ * path's edge factors (one path = one diagram).  Levels are evaluated in order,
+ * each completely before the next (Sec. II.C, "Windowing"), and many sample
+ * points (configurations) are evaluated at once (Sec. II.C, "Distributing the
+ * task on a grid of blocks").
+ *
+ * The graph is given in the flattened form of Fig. combinedgraphflat: per edge
+ * level, node-agnostic arrays of (src, dst) pairs.  The edge factor is the
+ * synthetic stand-in
+ *       w_e(x) = a_e / (1 + b_e * |x - k_e|^2),    x, k_e in R^3,
+ * for the Green's function an edge carries in the paper.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns a cos_status.  On failure cos_last_error() returns a
+ *    message for the calling thread; outputs are then undefined and no handle
+ *    is produced.  No C++ exception crosses this boundary.
+ *  - "host" pointers are read during the call only and stay owned by the
+ *    caller.  "device" pointers are HIP device allocations owned by the
+ *    caller, which keeps them alive until the work queued on `stream` ends.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is queued on it asynchronously, in stream order.
+ *  - Results are deterministic: the same graph, samples and precision give
+ *    bit-identical outputs on every call (no floating-point atomics).
+ */
+#ifndef COS_H
+#define COS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COS_ABI_VERSION 1
+
+typedef enum cos_status {
+    COS_OK = 0,
+    COS_EINVAL = -1,    /* malformed graph, sizes or pointers */
+    COS_ENOMEM = -2,    /* host or device allocation failed, or a request can never fit */
+    COS_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
+    COS_EAGAIN = -4,    /* serving: request not finished yet */
+    COS_ECANCELED = -5  /* serving: request was cancelled */
+} cos_status;
+
+typedef enum cos_precision {
+    /* binary64 node values and edge factors at every level */
+    COS_FP64 = 0,
+    /* binary32 node values and factors on interior levels with a power-of-two
+       rescale per (level, sample); binary64 final-node reduction and exponent
+       bookkeeping.  Single precision is the paper's own mode (Sec. III,
+       "Numerical stability"); the rescale is this library's addition. */
+    COS_FP32_RESCALED = 1,
+    /* as COS_FP32_RESCALED without the rescale (the paper's plain FP32) */
+    COS_FP32 = 2
+} cos_precision;
+
+typedef struct cos_graph cos_graph;
+
+typedef struct cos_graph_info {
+    int32_t L;               /* number of edge levels (node levels 0..L) */
+    int32_t reserved;
+    int64_t n_nodes;         /* sum of widths; the final node id is n_nodes - 1 */
+    int64_t n_edges;
+    int64_t max_width;       /* widest interior level (0 when L == 1) */
+    int64_t max_in_degree;   /* over interior levels 1..L-1 */
+    int64_t final_in_degree; /* in-edges of the final node */
+    uint64_t device_bytes;   /* device memory held by the graph */
+} cos_graph_info;
+
+/* Message for the last failed call on this thread ("" if none).  Owned by the
+   library; valid until the thread's next call. */
+const char *cos_last_error(void);
+
+/* Hash of the sources the library was built from (NUL-terminated, static). */
+const char *cos_build_id(void);
+
+/* COS_ABI_VERSION of the built library. */
+int32_t cos_abi_version(void);
+
+/*
+ * Build a device-resident graph from flattened per-level edge lists
+ * (Sec. II.C "Graph flattening", Fig. combinedgraphflat).  The graph is built
+ * once and evaluated many times (Sec. II.B: a graph is constructed once
+ * before any calculation).
+ *
+ *   L                 number of edge levels, >= 1
+ *   widths   host     int64[L+1]; widths[0] = widths[L] = 1, all >= 1,
+ *                     sum < 2^31.  Node ids are global and contiguous level
+ *                     by level: level l holds ids off_l .. off_l + widths[l]-1.
+ *   edges_per_level   host int64[L]; entry l-1 counts the edges into level l
+ *                     (an edge level is named by its destination level).
+ *   src, dst host     int32[E], E = sum(edges_per_level), level-major: the
+ *                     edges of level 1 first.  src must lie in level l-1 and
+ *                     dst in level l.  Any order within a level; parallel
+ *                     edges are separate terms; nodes without in-edges hold 0.
+ *   a, b     host     float64[E]: finite, b >= 0 (b = 0 gives w = a).
+ *   k        host     float64[E][3], finite.
+ *   out               receives the handle; release with cos_destroy_graph.
+ *
+ * The inputs are copied; the caller may free them on return.  Within each
+ * level the library stores edges in canonical order: by destination, then
+ * source, then the bit patterns of (a, b, k0, k1, k2), so every permutation of
+ * the same edge set yields the same device graph and bit-identical results.
+ * Errors: COS_EINVAL (validation), COS_ENOMEM, COS_EDEVICE.
+ */
+cos_status cos_create_graph(int32_t L, const int64_t *widths, const int64_t *edges_per_level,
+                            const int32_t *src, const int32_t *dst, const double *a,
+                            const double *b, const double *k, cos_graph **out);
+
+/* Sizes of a graph (see cos_graph_info).  Errors: COS_EINVAL on NULL. */
+cos_status cos_graph_get_info(const cos_graph *g, cos_graph_info *info);
+
+/*
+ * Copy the graph's edges back to host arrays of E entries (k: E*3), in the
+ * canonical order described at cos_create_graph, with global node ids.
+ * Errors: COS_EINVAL on NULL.
+ */
+cos_status cos_graph_export(const cos_graph *g, int32_t *src, int32_t *dst, double *a, double *b,
+                            double *k);
+
+/*
+ * Device scratch bytes cos_evaluate needs for S samples at precision p
+ * (level buffers, exponent rows and final-node partial sums).
+ * Errors: COS_EINVAL.
+ */
+cos_status cos_evaluate_workspace_size(const cos_graph *g, int64_t S, cos_precision p,
+                                       uint64_t *bytes);
+
+/*
+ * Evaluate the final-node value for S sample points (Sec. II.B; many
+ * configurations at once as in Sec. II.C).
+ *
+ *   x_dev        device float64[3][S]: x_dev[c*S + s] is coordinate c of
+ *                sample s (structure of arrays).
+ *   S            >= 0 (0: nothing is queued).
+ *   p            COS_FP64, COS_FP32_RESCALED or COS_FP32.
+ *   out_dev      device float64[S].  Without out_exp_dev: the value V(x_s).
+ *   out_exp_dev  device int32[S] or NULL.  When given, the result is returned
+ *                as out_dev[s] * 2^out_exp_dev[s] (for values whose magnitude
+ *                may leave the binary64 range); always 0 for COS_FP64.
+ *   workspace_dev, workspace_bytes
+ *                device scratch of at least cos_evaluate_workspace_size bytes,
+ *                256-byte aligned, used only by work queued on `stream`.
+ *                NULL: the library allocates and frees it in stream order
+ *                (hipMallocAsync / hipFreeAsync).
+ *   stream       hipStream_t as void*.
+ *
+ * Asynchronous: returns once the work is queued.  Errors: COS_EINVAL (NULL or
+ * misaligned pointers, bad S or precision, workspace too small), COS_ENOMEM,
+ * COS_EDEVICE (launch failure).
+ */
+cos_status cos_evaluate(const cos_graph *g, const double *x_dev, int64_t S, cos_precision p,
+                        double *out_dev, int32_t *out_exp_dev, void *workspace_dev,
+                        uint64_t workspace_bytes, void *stream);
+
+/* Release a graph and its device memory.  Must not race with queued work that
+   reads it.  NULL is a no-op.  Errors: COS_EDEVICE if hipFree fails. */
+cos_status cos_destroy_graph(cos_graph *g);
+
+/*
+ * Kernel timing probe (for benchmarks).  While enabled, every kernel the
+ * library queues is bracketed by a pair of HIP events recorded on the same
+ * stream.  cos_timing_read waits for the recorded events, returns the summed
+ * device time in milliseconds and the launch count for kernel class `kind`,
+ * and clears that class's records.  Kinds: 0 interior level gather,
+ * 1 fused multi-level (LDS-resident), 2 final-node partial sums,
+ * 3 final-node combine, 4 scratch fills, 5 serving step.
+ * Errors: COS_EINVAL (bad kind), COS_EDEVICE.
+ */
+cos_status cos_timing_enable(int32_t enable);
+cos_status cos_timing_read(int32_t kind, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COS_H */

@@ -1,0 +1,361 @@
+// Host side of the library: errors, graph ingest (validation, canonical order,
+// per-level CSR, parameter records), upload, introspection and the timing probe.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <numeric>
+
+#include "cos_internal.h"
+
+#ifndef COS_BUILD_ID
+#define COS_BUILD_ID "unknown"
+#endif
+
+struct cos_graph {
+    cosdag::Graph g;
+};
+
+namespace cosdag {
+
+static thread_local std::string t_error;
+
+void set_error(const std::string &msg) { t_error = msg; }
+
+cos_status fail(cos_status st, const std::string &msg) {
+    t_error = msg;
+    return st;
+}
+
+cos_status hip_fail(hipError_t err, const char *what) {
+    t_error = std::string(what) + ": " + hipGetErrorString(err);
+    return err == hipErrorOutOfMemory ? COS_ENOMEM : COS_EDEVICE;
+}
+
+// ---------------------------------------------------------------- timing probe
+namespace {
+struct TimingRec {
+    int kind;
+    hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<TimingRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+thread_local hipEvent_t t_open_start[KK_COUNT] = {};
+
+hipEvent_t take_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+}  // namespace
+
+bool timing_on() { return g_timing; }
+
+void timing_begin(int kind, hipStream_t s) {
+    if (!g_timing)
+        return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s) == hipSuccess)
+        t_open_start[kind] = e;
+}
+
+void timing_end(int kind, hipStream_t s) {
+    if (!g_timing || !t_open_start[kind])
+        return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, s) == hipSuccess)
+        g_recs.push_back({kind, t_open_start[kind], e});
+    t_open_start[kind] = nullptr;
+}
+
+}  // namespace cosdag
+
+using namespace cosdag;
+
+extern "C" const char *cos_last_error(void) { return t_error.c_str(); }
+extern "C" const char *cos_build_id(void) { return COS_BUILD_ID; }
+extern "C" int32_t cos_abi_version(void) { return COS_ABI_VERSION; }
+
+extern "C" cos_status cos_timing_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = enable != 0;
+    return COS_OK;
+}
+
+extern "C" cos_status cos_timing_read(int32_t kind, double *total_ms, int64_t *launches) {
+    if (kind < 0 || kind >= KK_COUNT || !total_ms || !launches)
+        return fail(COS_EINVAL, "cos_timing_read: bad kind or NULL output");
+    std::lock_guard<std::mutex> lk(g_tmu);
+    double tot = 0.0;
+    int64_t n = 0;
+    std::vector<TimingRec> keep;
+    for (const TimingRec &r : g_recs) {
+        if (r.kind != kind) {
+            keep.push_back(r);
+            continue;
+        }
+        hipError_t err = hipEventSynchronize(r.stop);
+        float ms = 0.f;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (err != hipSuccess)
+            return hip_fail(err, "cos_timing_read");
+        tot += ms;
+        ++n;
+        g_pool.push_back(r.start);
+        g_pool.push_back(r.stop);
+    }
+    g_recs.swap(keep);
+    *total_ms = tot;
+    *launches = n;
+    return COS_OK;
+}
+
+// ---------------------------------------------------------------- graph ingest
+namespace {
+
+uint64_t bits_of(double v) {
+    uint64_t u;
+    std::memcpy(&u, &v, sizeof u);
+    return u;
+}
+
+cos_status validate_shape(int32_t L, const int64_t *widths, const int64_t *epl, int64_t *n_nodes,
+                          int64_t *n_edges) {
+    if (L < 1)
+        return fail(COS_EINVAL, "L must be >= 1");
+    if (!widths || !epl)
+        return fail(COS_EINVAL, "widths / edges_per_level is NULL");
+    if (widths[0] != 1 || widths[L] != 1)
+        return fail(COS_EINVAL, "widths[0] and widths[L] must be 1 (single root, single final node)");
+    int64_t nn = 0, ne = 0;
+    for (int32_t l = 0; l <= L; ++l) {
+        if (widths[l] < 1)
+            return fail(COS_EINVAL, "widths[" + std::to_string(l) + "] < 1");
+        nn += widths[l];
+        if (nn >= INT32_MAX)
+            return fail(COS_EINVAL, "node count must be < 2^31");
+    }
+    for (int32_t l = 0; l < L; ++l) {
+        if (epl[l] < 0)
+            return fail(COS_EINVAL, "edges_per_level[" + std::to_string(l) + "] < 0");
+        ne += epl[l];
+        if (ne >= INT32_MAX)
+            return fail(COS_EINVAL, "edge count must be < 2^31");
+    }
+    *n_nodes = nn;
+    *n_edges = ne;
+    return COS_OK;
+}
+
+}  // namespace
+
+extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const int64_t *edges_per_level,
+                                       const int32_t *src, const int32_t *dst, const double *a,
+                                       const double *b, const double *k, cos_graph **out) {
+    try {
+        if (!out)
+            return fail(COS_EINVAL, "out is NULL");
+        *out = nullptr;
+        int64_t n_nodes = 0, n_edges = 0;
+        cos_status st = validate_shape(L, widths, edges_per_level, &n_nodes, &n_edges);
+        if (st != COS_OK)
+            return st;
+        if (n_edges > 0 && (!src || !dst || !a || !b || !k))
+            return fail(COS_EINVAL, "edge arrays are NULL");
+
+        auto h = std::make_unique<cos_graph>();
+        Graph &G = h->g;
+        G.L = L;
+        G.widths.assign(widths, widths + L + 1);
+        G.level_first.resize(L + 2);
+        G.level_first[0] = 0;
+        for (int32_t l = 0; l <= L; ++l)
+            G.level_first[l + 1] = G.level_first[l] + widths[l];
+        G.n_nodes = n_nodes;
+        G.n_edges = n_edges;
+
+        // validate every edge against its level and its parameters
+        int64_t e = 0;
+        for (int32_t l = 1; l <= L; ++l) {
+            const int64_t s_lo = G.level_first[l - 1], s_hi = G.level_first[l];
+            const int64_t d_lo = G.level_first[l], d_hi = G.level_first[l + 1];
+            for (int64_t i = 0; i < edges_per_level[l - 1]; ++i, ++e) {
+                if (src[e] < s_lo || src[e] >= s_hi || dst[e] < d_lo || dst[e] >= d_hi)
+                    return fail(COS_EINVAL, "edge " + std::to_string(e) + " (" + std::to_string(src[e]) + "->" +
+                                                std::to_string(dst[e]) + ") does not join level " +
+                                                std::to_string(l - 1) + " to level " + std::to_string(l));
+                if (!std::isfinite(a[e]) || !std::isfinite(b[e]) || b[e] < 0.0 || !std::isfinite(k[3 * e]) ||
+                    !std::isfinite(k[3 * e + 1]) || !std::isfinite(k[3 * e + 2]))
+                    return fail(COS_EINVAL, "edge " + std::to_string(e) +
+                                                ": parameters must be finite with b >= 0");
+            }
+        }
+
+        // canonical order within each level: (dst, src, bits of a, b, k0, k1, k2)
+        std::vector<int64_t> order(n_edges);
+        std::iota(order.begin(), order.end(), 0);
+        G.levels.resize(L);
+        int64_t e0 = 0, rp = 0;
+        for (int32_t l = 1; l <= L; ++l) {
+            const int64_t ne = edges_per_level[l - 1];
+            auto less = [&](int64_t i, int64_t j) {
+                if (dst[i] != dst[j])
+                    return dst[i] < dst[j];
+                if (src[i] != src[j])
+                    return src[i] < src[j];
+                const double pi[5] = {a[i], b[i], k[3 * i], k[3 * i + 1], k[3 * i + 2]};
+                const double pj[5] = {a[j], b[j], k[3 * j], k[3 * j + 1], k[3 * j + 2]};
+                for (int c = 0; c < 5; ++c)
+                    if (bits_of(pi[c]) != bits_of(pj[c]))
+                        return bits_of(pi[c]) < bits_of(pj[c]);
+                return false;
+            };
+            std::sort(order.begin() + e0, order.begin() + e0 + ne, less);
+            LevelDesc &d = G.levels[l - 1];
+            d.w_src = widths[l - 1];
+            d.w_dst = widths[l];
+            d.e_begin = e0;
+            d.n_edges = ne;
+            d.rp_begin = rp;
+            rp += d.w_dst + 1;
+            e0 += ne;
+        }
+
+        G.h_src.resize(n_edges);
+        G.h_dst.resize(n_edges);
+        G.h_a.resize(n_edges);
+        G.h_b.resize(n_edges);
+        G.h_k.resize(3 * n_edges);
+        for (int64_t i = 0; i < n_edges; ++i) {
+            const int64_t o = order[i];
+            G.h_src[i] = src[o];
+            G.h_dst[i] = dst[o];
+            G.h_a[i] = a[o];
+            G.h_b[i] = b[o];
+            G.h_k[3 * i] = k[3 * o];
+            G.h_k[3 * i + 1] = k[3 * o + 1];
+            G.h_k[3 * i + 2] = k[3 * o + 2];
+        }
+        order.clear();
+        order.shrink_to_fit();
+
+        // per-level CSR over destinations (global edge indices) and edge records
+        std::vector<int32_t> row_ptr(rp);
+        std::vector<EdgeF64> e64(n_edges);
+        std::vector<EdgeF32> e32(n_edges);
+        for (int32_t l = 1; l <= L; ++l) {
+            LevelDesc &d = G.levels[l - 1];
+            int32_t *r = row_ptr.data() + d.rp_begin;
+            const int64_t dfirst = G.level_first[l], sfirst = G.level_first[l - 1];
+            int64_t i = d.e_begin, maxdeg = 0;
+            for (int64_t j = 0; j < d.w_dst; ++j) {
+                r[j] = static_cast<int32_t>(i);
+                const int64_t start = i;
+                while (i < d.e_begin + d.n_edges && G.h_dst[i] == dfirst + j)
+                    ++i;
+                maxdeg = std::max(maxdeg, i - start);
+            }
+            r[d.w_dst] = static_cast<int32_t>(i);
+            d.max_deg = maxdeg;
+            if (l < L) {
+                G.max_width = std::max(G.max_width, d.w_dst);
+                G.max_in_degree = std::max(G.max_in_degree, maxdeg);
+            }
+            for (int64_t q = d.e_begin; q < d.e_begin + d.n_edges; ++q) {
+                const int32_t s_local = static_cast<int32_t>(G.h_src[q] - sfirst);
+                e64[q] = EdgeF64{G.h_k[3 * q], G.h_k[3 * q + 1], G.h_k[3 * q + 2], G.h_b[q], G.h_a[q], s_local, 0};
+                e32[q] = EdgeF32{static_cast<float>(G.h_k[3 * q]), static_cast<float>(G.h_k[3 * q + 1]),
+                                 static_cast<float>(G.h_k[3 * q + 2]), static_cast<float>(G.h_b[q]),
+                                 static_cast<float>(G.h_a[q]), s_local, 0, 0};
+            }
+        }
+
+        // one device allocation: row_ptr | e64 | e32
+        const size_t off_rp = 0;
+        const size_t off_64 = round_up(rp * sizeof(int32_t), 256);
+        const size_t off_32 = off_64 + round_up(n_edges * sizeof(EdgeF64), 256);
+        const size_t total = off_32 + round_up(n_edges * sizeof(EdgeF32), 256);
+        hipError_t err = hipGetDevice(&G.device);
+        if (err != hipSuccess)
+            return hip_fail(err, "hipGetDevice");
+        err = hipMalloc(&G.d_base, std::max<size_t>(total, 256));
+        if (err != hipSuccess)
+            return hip_fail(err, "hipMalloc(graph)");
+        G.d_bytes = std::max<size_t>(total, 256);
+        char *base = static_cast<char *>(G.d_base);
+        G.d_row_ptr = reinterpret_cast<int32_t *>(base + off_rp);
+        G.d_e64 = reinterpret_cast<EdgeF64 *>(base + off_64);
+        G.d_e32 = reinterpret_cast<EdgeF32 *>(base + off_32);
+        err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (err == hipSuccess && n_edges)
+            err = hipMemcpy(G.d_e64, e64.data(), n_edges * sizeof(EdgeF64), hipMemcpyHostToDevice);
+        if (err == hipSuccess && n_edges)
+            err = hipMemcpy(G.d_e32, e32.data(), n_edges * sizeof(EdgeF32), hipMemcpyHostToDevice);
+        if (err != hipSuccess) {
+            (void)hipFree(G.d_base);
+            return hip_fail(err, "hipMemcpy(graph)");
+        }
+        *out = h.release();
+        return COS_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(COS_ENOMEM, "host allocation failed in cos_create_graph");
+    } catch (...) {
+        return fail(COS_EDEVICE, "unexpected exception in cos_create_graph");
+    }
+}
+
+extern "C" cos_status cos_graph_get_info(const cos_graph *h, cos_graph_info *info) {
+    if (!h || !info)
+        return fail(COS_EINVAL, "cos_graph_get_info: NULL argument");
+    const Graph &G = h->g;
+    info->L = G.L;
+    info->reserved = 0;
+    info->n_nodes = G.n_nodes;
+    info->n_edges = G.n_edges;
+    info->max_width = G.max_width;
+    info->max_in_degree = G.max_in_degree;
+    info->final_in_degree = G.levels.back().n_edges;
+    info->device_bytes = G.d_bytes;
+    return COS_OK;
+}
+
+extern "C" cos_status cos_graph_export(const cos_graph *h, int32_t *src, int32_t *dst, double *a, double *b,
+                                       double *k) {
+    if (!h || !src || !dst || !a || !b || !k)
+        return fail(COS_EINVAL, "cos_graph_export: NULL argument");
+    const Graph &G = h->g;
+    const size_t n = static_cast<size_t>(G.n_edges);
+    std::memcpy(src, G.h_src.data(), n * sizeof(int32_t));
+    std::memcpy(dst, G.h_dst.data(), n * sizeof(int32_t));
+    std::memcpy(a, G.h_a.data(), n * sizeof(double));
+    std::memcpy(b, G.h_b.data(), n * sizeof(double));
+    std::memcpy(k, G.h_k.data(), 3 * n * sizeof(double));
+    return COS_OK;
+}
+
+extern "C" cos_status cos_destroy_graph(cos_graph *h) {
+    if (!h)
+        return COS_OK;
+    hipError_t err = h->g.d_base ? hipFree(h->g.d_base) : hipSuccess;
+    delete h;
+    if (err != hipSuccess)
+        return hip_fail(err, "hipFree(graph)");
+    return COS_OK;
+}
+
+// accessor for the other translation units
+namespace cosdag {
+const Graph &graph_of(const cos_graph *h) { return h->g; }
+}  // namespace cosdag

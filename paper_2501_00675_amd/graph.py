@@ -1,0 +1,122 @@
+"""Python face of the C ABI: device-resident graphs and their evaluation.
+
+Only argument marshalling happens here; every step of the evaluation runs in
+the library's HIP kernels.  torch provides device memory and the stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import KINDS, LIB, PRECISIONS, GraphInfo, check
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Graph:
+    """A leveled DAG held on the current HIP device (cos_create_graph)."""
+
+    def __init__(self, L, widths, edges_per_level, src, dst, a, b, k):
+        keep = []
+
+        def ptr(v, dt):
+            arr, p = _c(v, dt)
+            keep.append(arr)
+            return p
+
+        h = ctypes.c_void_p()
+        st = LIB.cos_create_graph(int(L), ptr(widths, np.int64), ptr(edges_per_level, np.int64),
+                                  ptr(src, np.int32), ptr(dst, np.int32), ptr(a, np.float64),
+                                  ptr(b, np.float64), ptr(np.reshape(k, -1), np.float64), ctypes.byref(h))
+        check(st, "cos_create_graph")
+        self._h = h
+
+    @classmethod
+    def from_leveled(cls, g) -> "Graph":
+        """From any object with L, widths, epl, src, dst, a, b, k (e.g. workloads.LeveledGraph)."""
+        return cls(g.L, g.widths, g.epl, g.src, g.dst, g.a, g.b, g.k)
+
+    @property
+    def handle(self) -> int:
+        if self._h is None:
+            raise ValueError("graph was destroyed")
+        return self._h.value
+
+    def info(self) -> dict:
+        gi = GraphInfo()
+        check(LIB.cos_graph_get_info(self.handle, ctypes.byref(gi)), "cos_graph_get_info")
+        return {f: getattr(gi, f) for f, _ in GraphInfo._fields_ if f != "reserved"}
+
+    def export(self) -> dict:
+        E = self.info()["n_edges"]
+        out = dict(src=np.empty(E, np.int32), dst=np.empty(E, np.int32), a=np.empty(E), b=np.empty(E),
+                   k=np.empty((E, 3)))
+        check(LIB.cos_graph_export(self.handle, *[out[n].ctypes.data_as(ctypes.c_void_p)
+                                                  for n in ("src", "dst", "a", "b", "k")]), "cos_graph_export")
+        return out
+
+    def workspace_bytes(self, S: int, precision: str = "fp64") -> int:
+        v = ctypes.c_uint64()
+        check(LIB.cos_evaluate_workspace_size(self.handle, int(S), PRECISIONS[precision], ctypes.byref(v)),
+              "cos_evaluate_workspace_size")
+        return int(v.value)
+
+    def evaluate(self, x: torch.Tensor, precision: str = "fp64", out: torch.Tensor | None = None,
+                 out_exp: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                 stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """Final-node value for the samples x (float64[3, S] on the device), queued on `stream`."""
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 2
+                and x.shape[0] == 3 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous float64 CUDA tensor of shape [3, S]")
+        S = x.shape[1]
+        if out is None:
+            out = torch.empty(S, dtype=torch.float64, device=x.device)
+        if not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= S and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 CUDA tensor with >= S elements")
+        if out_exp is not None and not (out_exp.is_cuda and out_exp.dtype == torch.int32
+                                        and out_exp.numel() >= S and out_exp.is_contiguous()):
+            raise ValueError("out_exp must be a contiguous int32 CUDA tensor with >= S elements")
+        need = self.workspace_bytes(S, precision)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+        if workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        check(LIB.cos_evaluate(self.handle, x.data_ptr(), S, PRECISIONS[precision], out.data_ptr(),
+                               out_exp.data_ptr() if out_exp is not None else None, workspace.data_ptr(),
+                               workspace.numel() * workspace.element_size(), st.cuda_stream), "cos_evaluate")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(LIB.cos_destroy_graph(self._h.value), "cos_destroy_graph")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def timing_enable(on: bool = True):
+    check(LIB.cos_timing_enable(1 if on else 0), "cos_timing_enable")
+
+
+def timing_read(kind: str) -> tuple[float, int]:
+    """(total device ms, launches) recorded for a kernel class since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    check(LIB.cos_timing_read(KINDS[kind], ctypes.byref(ms), ctypes.byref(n)), "cos_timing_read")
+    return ms.value, n.value

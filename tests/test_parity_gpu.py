@@ -1,0 +1,279 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances: per-sample |y - r| / max(|r|, sqrt(Q)) <= 1e-12 for FP64 and
+<= 1e-5 for the FP32 paths, where r is the oracle's FP64 value and Q the
+squared 2-norm of the path terms; integer-valued results (path counts) must be
+bit-exact.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pins
+from gpu_util import PRECISIONS, assert_parity, gpu_eval, oracle_ref, sample_subset, say, to_dev
+from workloads import LeveledGraph, layered_graph, make_config, transpose
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2501_00675_amd as P
+
+    assert torch.cuda.is_available()
+    return P
+
+
+def graph(P, g):
+    return P.Graph.from_leveled(g)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_paper_figure_all_ones(P, precision):
+    g, expect = pins.load_figure_graph()
+    x = np.random.default_rng(1).uniform(-1, 1, (3, 300))
+    y = gpu_eval(graph(P, g), x, precision)
+    assert np.all(y == expect)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_tiny_parity(P, precision):
+    g, x = make_config("tiny")
+    say(f"tiny {precision} S={x.shape[1]}")
+    y = gpu_eval(graph(P, g), x, precision)
+    V, Q = oracle_ref(g, x)
+    assert_parity(y, V, Q, precision, "tiny")
+
+
+@pytest.mark.parametrize("S", [1, 2, 63, 64, 65, 127, 255, 257, 1000])
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_ragged_sample_counts(P, S, precision):
+    g, x = make_config("mid", S=S, width=40, L=6)
+    say(f"ragged {precision} S={S}")
+    y = gpu_eval(graph(P, g), x, precision)
+    V, Q = oracle_ref(g, x)
+    assert_parity(y, V, Q, precision, f"ragged S={S}")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_mid_full_size_sampled(P, precision):
+    g, x = make_config("mid")
+    say(f"mid full {precision}")
+    y = gpu_eval(graph(P, g), x, precision)
+    idx = sample_subset(x.shape[1], 512)
+    V, Q = oracle_ref(g, x, idx)
+    assert np.all(np.isfinite(y))
+    assert_parity(y[idx], V, Q, precision, "mid")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_precision_full_size_sampled(P, precision):
+    g, x = make_config("precision")
+    say(f"precision full {precision}")
+    y = gpu_eval(graph(P, g), x, precision)
+    idx = sample_subset(x.shape[1], 192)
+    V, Q = oracle_ref(g, x, idx)
+    assert_parity(y[idx], V, Q, precision, "precision")
+
+
+@pytest.mark.slow
+def test_large_full_size_sampled(P):
+    g, x = make_config("large")
+    G = graph(P, g)
+    idx = sample_subset(x.shape[1], 24)
+    V, Q = oracle_ref(g, x, idx)
+    for precision in ("fp64", "fp32r"):
+        say(f"large full {precision}")
+        y = gpu_eval(G, x, precision)
+        assert_parity(y[idx], V, Q, precision, "large")
+
+
+@pytest.mark.parametrize("name,expect", [("tiny", 12), ("mid", 2 ** 28), ("precision", 2 ** 78)])
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_all_ones_path_counts_exact(P, name, expect, precision):
+    g, x = make_config(name, S=300)
+    g1 = g.with_params(a=1.0, b=0.0, k=0.0)
+    y = gpu_eval(graph(P, g1), x, precision)
+    assert np.all(y == float(expect)), (y[:4], expect)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_level_constant_closed_form(P, precision):
+    rng = np.random.default_rng(7)
+    g, x = make_config("mid", S=512)
+    gc, (al, bl, kl) = pins.level_constant_graph(g, rng)
+    d = pins.in_degrees(g)
+    cf = np.ones(x.shape[1])
+    for l in range(g.L):
+        cf = cf * (d[l] * al[l] / (1.0 + bl[l] * ((x - kl[l][:, None]) ** 2).sum(0)))
+    y = gpu_eval(graph(P, gc), x, precision)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.max(np.abs(y - cf) / np.abs(cf)) <= tol
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_bit_reproducible(P, precision):
+    g, x = make_config("precision", S=1000)
+    G = graph(P, g)
+    y1 = gpu_eval(G, x, precision)
+    y2 = gpu_eval(G, x, precision)
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+
+
+def test_input_permutation_gives_identical_graph_and_bits(P):
+    g, x = make_config("mid", S=700)
+    rng = np.random.default_rng(3)
+    gp = g.copy()
+    for sl in g.level_slices():
+        perm = rng.permutation(sl.stop - sl.start) + sl.start
+        gp.src[sl], gp.dst[sl], gp.a[sl], gp.b[sl], gp.k[sl] = (g.src[perm], g.dst[perm], g.a[perm], g.b[perm],
+                                                                 g.k[perm])
+    G1, G2 = graph(P, g), graph(P, gp)
+    e1, e2 = G1.export(), G2.export()
+    for n in e1:
+        assert np.array_equal(e1[n], e2[n])
+    for precision in ("fp64", "fp32r"):
+        assert np.array_equal(gpu_eval(G1, x, precision), gpu_eval(G2, x, precision))
+
+
+def test_export_is_canonical_sort_of_input(P):
+    g, _ = make_config("tiny", S=1, order="shuffle")
+    e = graph(P, g).export()
+    for sl in g.level_slices():
+        bits = [np.asarray(v).view(np.uint64) for v in (g.k[sl, 2], g.k[sl, 1], g.k[sl, 0], g.b[sl], g.a[sl])]
+        order = np.lexsort((*bits, g.src[sl], g.dst[sl])) + sl.start
+        assert np.array_equal(e["dst"][sl], g.dst[order]) and np.array_equal(e["src"][sl], g.src[order])
+        assert np.array_equal(e["a"][sl], g.a[order]) and np.array_equal(e["k"][sl], g.k[order])
+
+
+def test_fp32_rescaled_equals_unscaled_on_benign_graph(P):
+    # power-of-two scaling is exact: with no under/overflow the two FP32 paths agree bit for bit
+    g, x = make_config("mid", S=1024)
+    G = graph(P, g)
+    assert np.array_equal(gpu_eval(G, x, "fp32r"), gpu_eval(G, x, "fp32"))
+
+
+def test_out_exp_form(P):
+    g, x = make_config("precision", S=300)
+    G = graph(P, g)
+    xd = to_dev(x)
+    e = torch.empty(x.shape[1], dtype=torch.int32, device=xd.device)
+    m = G.evaluate(xd, "fp32r", out_exp=e)
+    y = G.evaluate(xd, "fp32r")
+    torch.cuda.synchronize()
+    assert np.array_equal(np.ldexp(m.cpu().numpy(), e.cpu().numpy()), y.cpu().numpy())
+    e64 = torch.full((x.shape[1],), 7, dtype=torch.int32, device=xd.device)
+    G.evaluate(xd, "fp64", out_exp=e64)
+    torch.cuda.synchronize()
+    assert int(e64.abs().max()) == 0
+
+
+def test_rescale_prevents_fp32_underflow(P):
+    # 40 levels of factors ~2^-6: the value ~2^-240 underflows binary32 but not binary64
+    rng = np.random.default_rng(11)
+    g = layered_graph([1] + [8] * 39 + [1], 2, rng)
+    E = g.n_edges
+    g = g.with_params(a=rng.uniform(0.5, 1.0, E) * 2.0 ** -7, b=rng.uniform(0.5, 2, E), k=rng.uniform(-1, 1, (E, 3)))
+    x = rng.uniform(-1, 1, (3, 256))
+    V, Q = oracle_ref(g, x)
+    assert np.all(np.abs(V) < 2.0 ** -200)
+    G = graph(P, g)
+    assert_parity(gpu_eval(G, x, "fp32r"), V, Q, "fp32r", "underflow")
+    assert np.all(gpu_eval(G, x, "fp32") == 0.0)
+    assert_parity(gpu_eval(G, x, "fp64"), V, Q, "fp64", "underflow")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_single_edge_level_and_parallel_edges(P, precision):
+    # L = 1: root joined to the final node by three parallel edges
+    g = LeveledGraph(np.array([1, 1]), np.array([3]), np.zeros(3, np.int32), np.ones(3, np.int32),
+                     np.array([0.5, -0.25, 2.0]), np.array([0.0, 1.0, 0.5]), np.zeros((3, 3)))
+    x = np.random.default_rng(2).uniform(-1, 1, (3, 70))
+    V, Q = oracle_ref(g, x)
+    assert_parity(gpu_eval(graph(P, g), x, precision), V, Q, precision, "L=1")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_zero_in_degree_nodes_and_empty_level(P, precision):
+    rng = np.random.default_rng(4)
+    g = layered_graph([1, 5, 6, 4, 1], [1, 2, 2, 4], rng, cover=False)
+    g = g.with_params(a=rng.uniform(-1, 1, g.n_edges), b=rng.uniform(0, 2, g.n_edges),
+                      k=rng.uniform(-1, 1, (g.n_edges, 3)))
+    keep = np.ones(g.n_edges, bool)
+    sl = g.level_slices()[2]
+    keep[sl.start:sl.start + 3] = False  # some level-3 nodes lose in-edges
+    g2 = LeveledGraph(g.widths, np.array([int(keep[s].sum()) for s in g.level_slices()]), g.src[keep], g.dst[keep],
+                      g.a[keep], g.b[keep], g.k[keep])
+    x = rng.uniform(-1, 1, (3, 100))
+    V, Q = oracle_ref(g2, x)
+    assert_parity(gpu_eval(graph(P, g2), x, precision), V, Q, precision, "zero-in-degree")
+    g3 = LeveledGraph(np.array([1, 2, 1]), np.array([2, 0]), np.zeros(2, np.int32), np.array([1, 2], np.int32),
+                      np.ones(2), np.zeros(2), np.zeros((2, 3)))
+    assert np.all(gpu_eval(graph(P, g3), x, precision) == 0.0)
+
+
+def test_transpose_agrees(P):
+    g, x = make_config("mid", S=256, seed=9)
+    y = gpu_eval(graph(P, g), x, "fp64")
+    yt = gpu_eval(graph(P, transpose(g)), x, "fp64")
+    V, Q = oracle_ref(g, x)
+    assert_parity(y, V, Q, "fp64", "G")
+    assert_parity(yt, V, Q, "fp64", "G^T")
+
+
+def test_zero_samples_queue_nothing(P):
+    g, _ = make_config("tiny", S=1)
+    G = graph(P, g)
+    xd = torch.empty((3, 0), dtype=torch.float64, device="cuda:0")
+    out = G.evaluate(xd, "fp64")
+    assert out.numel() == 0
+
+
+def test_workspace_checks(P):
+    g, x = make_config("tiny", S=100)
+    G = graph(P, g)
+    xd = to_dev(x)
+    need = G.workspace_bytes(100, "fp64")
+    ws = torch.empty(need + 512, dtype=torch.uint8, device=xd.device)
+    with pytest.raises(ValueError):
+        G.evaluate(xd, "fp64", workspace=ws[: need - 8])
+    with pytest.raises(P.CosError):
+        G.evaluate(xd, "fp64", workspace=ws[8:])  # misaligned
+    y = G.evaluate(xd, "fp64", workspace=ws)
+    torch.cuda.synchronize()
+    V, Q = oracle_ref(g, x)
+    assert_parity(y.cpu().numpy(), V, Q, "fp64", "workspace")
+
+
+def test_side_stream(P):
+    g, x = make_config("mid", S=2048, width=64)
+    G = graph(P, g)
+    xd = to_dev(x)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        y = G.evaluate(xd, "fp64", stream=s)
+    s.synchronize()
+    V, Q = oracle_ref(g, x)
+    assert_parity(y.cpu().numpy(), V, Q, "fp64", "side stream")
+
+
+def test_timing_probe_counts_launches(P):
+    g, x = make_config("mid", S=1024)
+    G = graph(P, g)
+    xd = to_dev(x)
+    for kind in ("level", "final_partial", "final_combine", "fill", "fused"):
+        P.timing_read(kind)
+    P.timing_enable(True)
+    try:
+        G.evaluate(xd, "fp64")
+        torch.cuda.synchronize()
+        ms_l, n_l = P.timing_read("level")
+        ms_f, n_f = P.timing_read("fused")
+        ms_p, n_p = P.timing_read("final_partial")
+    finally:
+        P.timing_enable(False)
+    assert n_p == 1 and ms_p > 0
+    assert n_l + n_f >= 1 and ms_l + ms_f > 0
