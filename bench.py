@@ -154,10 +154,44 @@ def roofline(g, S_pad, precision, kern, steps):
                   "launches_per_step": n_launch, "algorithmic_bytes_per_launch": bytes_step / n_launch,
                   "other_term": ({"alu_tflops": alu, "alu_frac": f_a} if r["bound"] == "hbm"
                                  else {"hbm_gbs": hbm, "hbm_frac": f_h})})
+    elif dom == "fused":
+        # whole graph per launch with levels in LDS: every edge-sample of every level, 13 flops each
+        es_step = float(g.n_edges) * S_pad
+        t_launch = kern[dom]["total_ms"] / 1000.0 / kern[dom]["launches"]
+        n_launch = kern[dom]["launches"] / steps
+        alu = es_step / n_launch * FLOPS_PER_EDGE_SAMPLE / t_launch / 1e12
+        # compulsory HBM bytes: x in, out written, edge records read once per 64-sample workgroup
+        hbm_bytes = S_pad * (24 + 8) + g.n_edges * 64 * (S_pad // 64)
+        r = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+             "frac": alu / VALU_PEAK_TFLOPS[precision], "kernel": "fused_sweep_kernel",
+             "avg_launch_us": kern[dom]["avg_us"], "launches_per_step": n_launch,
+             "algorithmic_flops_per_launch": es_step / n_launch * FLOPS_PER_EDGE_SAMPLE,
+             "other_term": {"hbm_gbs_compulsory": hbm_bytes / t_launch / 1e9}}
     else:
         r = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "kernel": dom}
     r["traffic"] = None
     return r
+
+
+def calibrate_copy(steps: int, nbytes: int = 1 << 30):
+    """A plain device-to-device copy of nbytes: reads nbytes and writes nbytes per launch."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": nbytes,
+                      "bytes_written_per_launch": nbytes, "ms_per_launch": ms,
+                      "copy_GBps": 2 * nbytes / (ms / 1000) / 1e9}), flush=True)
 
 
 def main():
@@ -170,7 +204,12 @@ def main():
     ap.add_argument("--variants", default="fp32r", help="comma list of extra precisions to time ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="time a plain 1 GiB device copy (reference for HBM counters and bandwidth)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.steps)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards over samples with no "
                                    "per-level exchange (see the design notes), but no multi-GPU run is provided",

@@ -66,9 +66,16 @@ typedef enum cos_precision {
 
 typedef struct cos_graph cos_graph;
 
+/* Kernel plan of cos_evaluate (see cos_graph_set_path). */
+typedef enum cos_path {
+    COS_PATH_AUTO = 0,     /* fused when the widest level fits in LDS, else streamed */
+    COS_PATH_STREAMED = 1, /* one launch per level, level values streamed through HBM */
+    COS_PATH_FUSED = 2     /* one launch for the whole graph, level values held in LDS */
+} cos_path;
+
 typedef struct cos_graph_info {
     int32_t L;               /* number of edge levels (node levels 0..L) */
-    int32_t reserved;
+    int32_t fused_mask;      /* bit p set: the fused plan fits for cos_precision p */
     int64_t n_nodes;         /* sum of widths; the final node id is n_nodes - 1 */
     int64_t n_edges;
     int64_t max_width;       /* widest interior level (0 when L == 1) */
@@ -119,6 +126,18 @@ cos_status cos_create_graph(int32_t L, const int64_t *widths, const int64_t *edg
 
 /* Sizes of a graph (see cos_graph_info).  Errors: COS_EINVAL on NULL. */
 cos_status cos_graph_get_info(const cos_graph *g, cos_graph_info *info);
+
+/*
+ * Choose the kernel plan later cos_evaluate calls on this graph use.  Both
+ * plans compute the same arithmetic in the same order and give bit-identical
+ * results; the choice only moves the level values between HBM (streamed) and
+ * LDS (fused, for graphs whose widest level fits on chip -- the paper's small
+ * low-order graphs, Sec. III).  COS_PATH_FUSED on a graph or precision it does
+ * not fit makes cos_evaluate fail with COS_EINVAL.  Not thread-safe with
+ * respect to concurrent cos_evaluate calls on the same graph.
+ * Errors: COS_EINVAL (NULL graph, unknown path).
+ */
+cos_status cos_graph_set_path(cos_graph *g, cos_path path);
 
 /*
  * Copy the graph's edges back to host arrays of E entries (k: E*3), in the

@@ -1,6 +1,8 @@
 """Build libcosdag.so (host runtime + HIP kernels for gfx950) in-tree with hipcc.
 
-    python -m paper_2501_00675_amd._build
+    python paper_2501_00675_amd/_build.py
+
+(run as a script: importing the package loads the library it builds)
 """
 
 from __future__ import annotations

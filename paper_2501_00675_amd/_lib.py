@@ -28,8 +28,9 @@ KINDS = {"level": 0, "fused": 1, "final_partial": 2, "final_combine": 3, "fill":
 EXPORTS = [
     "cos_last_error", "cos_build_id", "cos_abi_version", "cos_create_graph", "cos_graph_get_info",
     "cos_graph_export", "cos_evaluate_workspace_size", "cos_evaluate", "cos_destroy_graph",
-    "cos_timing_enable", "cos_timing_read",
+    "cos_timing_enable", "cos_timing_read", "cos_graph_set_path",
 ]
+PATHS = {"auto": 0, "streamed": 1, "fused": 2}
 
 
 class CosError(RuntimeError):
@@ -39,7 +40,7 @@ class CosError(RuntimeError):
 
 
 class GraphInfo(ctypes.Structure):
-    _fields_ = [("L", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
+    _fields_ = [("L", ctypes.c_int32), ("fused_mask", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_edges", ctypes.c_int64), ("max_width", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
                 ("final_in_degree", ctypes.c_int64), ("device_bytes", ctypes.c_uint64)]
 
@@ -67,6 +68,8 @@ def _bind(lib):
     lib.cos_graph_get_info.argtypes = [p, ctypes.POINTER(GraphInfo)]
     lib.cos_graph_export.restype = i32
     lib.cos_graph_export.argtypes = [p, p, p, p, p, p]
+    lib.cos_graph_set_path.restype = i32
+    lib.cos_graph_set_path.argtypes = [p, i32]
     lib.cos_evaluate_workspace_size.restype = i32
     lib.cos_evaluate_workspace_size.argtypes = [p, i64, i32, ctypes.POINTER(u64)]
     lib.cos_evaluate.restype = i32
@@ -82,14 +85,14 @@ def _bind(lib):
 
 def load(path: str = LIB_PATH, check_stale: bool = True):
     if not os.path.exists(path):
-        raise ImportError(f"{path} is not built: run `python -m paper_2501_00675_amd._build` "
+        raise ImportError(f"{path} is not built: run `python paper_2501_00675_amd/_build.py` "
                           "(there is no CPU fallback)")
     lib = _bind(ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL))
     if check_stale and os.path.isdir(_build.CSRC):
         built, current = lib.cos_build_id().decode(), _build.source_hash()
         if built != current:
             raise ImportError(f"{path} was built from other sources (build id {built}, sources {current}); "
-                              "rebuild with `python -m paper_2501_00675_amd._build`")
+                              "rebuild with `python paper_2501_00675_amd/_build.py`")
     rts = _hip_runtimes_mapped()
     if len(rts) > 1:
         raise ImportError(f"two HIP runtimes are loaded ({sorted(rts)}); import torch before this package")

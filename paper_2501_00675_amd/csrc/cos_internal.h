@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -11,22 +12,26 @@
 
 namespace cosdag {
 
-// Device edge records, one per edge in canonical (dst, src, params) order.
-// Each is read with scalar loads by a whole wavefront: every lane of a wave
-// works on the same edge for different samples, so the record is uniform.
-struct alignas(16) EdgeF64 {
-    double k0, k1, k2, b, a;
-    int32_t src;  // index of the source node within the previous level
-    int32_t pad;
+// Device edge record, one per edge in canonical (dst, src, params) order,
+// 64 bytes so a wavefront fetches it with one scalar load: every lane of a
+// wave works on the same edge for different samples, so the record is
+// wave-uniform.  The denominator of the edge factor is stored expanded,
+//     1 + b |x - k|^2 = c0 + cb |x|^2 + g . x,
+//     c0 = 1 + b |k|^2,  cb = b,  g = -2 b k,
+// so that with |x|^2 kept per lane it costs four fused multiply-adds.
+struct alignas(16) EdgeRec {
+    double c0, cb, g0, g1, g2;
+    double a;
+    int32_t src;        // index of the source node within the previous level
+    float a32;          // a rounded to binary32 (nearest even)
+    int32_t row_end;    // 1 if this is the last edge into its destination node
+    int32_t zero_rows;  // nodes without in-edges that directly follow that destination
 };
-static_assert(sizeof(EdgeF64) == 48, "EdgeF64 layout");
+static_assert(sizeof(EdgeRec) == 64, "EdgeRec layout");
 
-struct alignas(16) EdgeF32 {
-    float k0, k1, k2, b, a;
-    int32_t src;
-    int32_t pad0, pad1;
-};
-static_assert(sizeof(EdgeF32) == 32, "EdgeF32 layout");
+// The device edge array carries this many zeroed records after the last edge,
+// so that kernels may fetch records in fixed-size chunks without bounds tests.
+constexpr int kEdgePad = 4;
 
 // Per edge level l = 1..L (stored at index l-1).
 struct LevelDesc {
@@ -36,6 +41,14 @@ struct LevelDesc {
     int64_t n_edges;
     int64_t rp_begin;  // offset of this level's row_ptr[w_dst + 1] in the row_ptr array
     int64_t max_deg;   // largest in-degree in this level
+};
+
+// Compact level table read by the fused kernel (device copy).
+struct LevelDev {
+    int32_t w_dst;
+    int32_t rp_begin;
+    int32_t e_begin;
+    int32_t n_edges;
 };
 
 struct Graph {
@@ -53,9 +66,10 @@ struct Graph {
     void *d_base = nullptr;
     size_t d_bytes = 0;
     int32_t *d_row_ptr = nullptr;     // global edge indices, per level w_dst+1 entries
-    EdgeF64 *d_e64 = nullptr;
-    EdgeF32 *d_e32 = nullptr;
+    EdgeRec *d_edges = nullptr;
+    LevelDev *d_levels = nullptr;     // L entries
     int device = 0;
+    cos_path path = COS_PATH_AUTO;    // kernel plan chosen by cos_graph_set_path
 };
 
 const Graph &graph_of(const cos_graph *h);
@@ -82,29 +96,45 @@ struct TimedLaunch {
 
 // ---------------------------------------------------------------- launch plans
 constexpr int kWave = 64;
-constexpr int kBlock = 256;          // 4 wavefronts per workgroup
+constexpr int kBlock = 256;          // 4 wavefronts per workgroup (streamed kernels)
 constexpr int kSamplePad = 256;      // S is padded to a multiple of this
+constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
+constexpr int kFinalChunk = 256;     // final-node edges per partial sum (4 quarters of 64)
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Workspace layout of one evaluate call.
+// Workspace layout of one evaluate call.  The streamed plan sweeps the graph
+// once per chunk of S_chunk samples (S_pad = S_chunk rounded to kSamplePad);
+// a chunk's level buffer stays below kMaxLevelBytes so kernels can address
+// rows with 32-bit byte offsets.
 struct Workspace {
     size_t bytes = 0;
     size_t off_buf0 = 0, off_buf1 = 0, off_maxbits = 0, off_partial = 0;
-    int64_t S_pad = 0;
-    int64_t level_elems = 0;   // max_width * S_pad
+    int64_t S_chunk = 0;       // samples per sweep
+    int64_t S_pad = 0;         // row length of the level buffers
     int32_t final_chunks = 0;  // partial sums of the final node
+    bool fused = false;        // whole sweep in the LDS-resident kernel
 };
+constexpr int64_t kMaxLevelBytes = int64_t(1) << 31;
+// Layout for sweeps of at most S_chunk samples (S_chunk > 0).
+Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p);
+// Natural plan for S samples: fused if it fits, else the largest chunk allowed.
 Workspace plan_workspace(const Graph &g, int64_t S, cos_precision p);
 
-// Kernel launchers (kernels_level.hip).  All return hipSuccess or the launch error.
+// Kernel launchers.  All return hipSuccess or the launch error.  x points at
+// the chunk's first sample; xs is the distance between coordinate rows of x.
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur,
-                        int64_t ld, const double *x, int64_t S, const uint32_t *prev_max,
+                        int64_t ld, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
                         uint32_t *cur_max, hipStream_t s);
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld,
-                        const double *x, int64_t S, const uint32_t *maxbits, double *partial,
+                        const double *x, int64_t S, int64_t xs, const uint32_t *maxbits, double *partial,
                         int32_t chunks, double *out, int32_t *out_exp, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// LDS-resident whole-graph sweep (kernels_fused.hip).
+bool fused_fits(const Graph &g, cos_precision p);
+hipError_t launch_fused(const Graph &g, cos_precision p, const double *x, int64_t S, double *out,
+                        int32_t *out_exp, hipStream_t s);
 
 int32_t final_chunk_count(int64_t final_in_degree);
 

@@ -1,28 +1,53 @@
-// cos_evaluate: workspace planning and the per-level launch sequence.
+// cos_evaluate: plan (fused or streamed, sample chunks), workspace layout and
+// the per-level launch sequence.
 #include <algorithm>
 
 #include "cos_internal.h"
 
 namespace cosdag {
 
-Workspace plan_workspace(const Graph &g, int64_t S, cos_precision p) {
+namespace {
+size_t elem_size(cos_precision p) { return p == COS_FP64 ? sizeof(double) : sizeof(float); }
+}  // namespace
+
+// Largest chunk (multiple of kSamplePad) whose level buffer stays below
+// kMaxLevelBytes; 0 if even kSamplePad samples do not.
+int64_t max_chunk(const Graph &g, cos_precision p) {
+    const int64_t w = std::max<int64_t>(g.max_width, 1);
+    const int64_t cap = (kMaxLevelBytes - 1) / (w * static_cast<int64_t>(elem_size(p)));
+    return cap / kSamplePad * kSamplePad;
+}
+
+Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p) {
     Workspace w;
-    w.S_pad = round_up(std::max<int64_t>(S, 1), kSamplePad);
-    const size_t elem = p == COS_FP64 ? sizeof(double) : sizeof(float);
-    w.level_elems = g.max_width * w.S_pad;
+    w.S_chunk = S_chunk;
+    w.S_pad = round_up(std::max<int64_t>(S_chunk, 1), kSamplePad);
+    const size_t level_bytes = static_cast<size_t>(g.max_width * w.S_pad) * elem_size(p);
     size_t off = 0;
     auto take = [&](size_t n) {
         const size_t o = off;
-        off = round_up(static_cast<int64_t>(off + n), 256);
+        off = static_cast<size_t>(round_up(static_cast<int64_t>(off + n), 256));
         return o;
     };
-    w.off_buf0 = take(w.level_elems * elem);
-    w.off_buf1 = take(w.level_elems * elem);
+    w.off_buf0 = take(level_bytes);
+    w.off_buf1 = take(level_bytes);
     w.off_maxbits = p == COS_FP32_RESCALED ? take(static_cast<size_t>(g.L + 1) * w.S_pad * sizeof(uint32_t)) : 0;
     w.final_chunks = final_chunk_count(g.levels.back().n_edges);
     w.off_partial = take(static_cast<size_t>(w.final_chunks) * w.S_pad * sizeof(double));
     w.bytes = std::max<size_t>(off, 256);
     return w;
+}
+
+Workspace plan_workspace(const Graph &g, int64_t S, cos_precision p) {
+    Workspace w;
+    w.fused = g.path == COS_PATH_FUSED || (g.path == COS_PATH_AUTO && fused_fits(g, p));
+    if (w.fused) {  // levels live in LDS: no device scratch
+        w.S_chunk = S;
+        w.bytes = 256;
+        return w;
+    }
+    const int64_t cap = max_chunk(g, p);
+    return layout_for_chunk(g, std::min<int64_t>(std::max<int64_t>(S, 1), std::max<int64_t>(cap, 1)), p);
 }
 
 }  // namespace cosdag
@@ -31,6 +56,28 @@ using namespace cosdag;
 
 namespace {
 bool valid_precision(cos_precision p) { return p == COS_FP64 || p == COS_FP32_RESCALED || p == COS_FP32; }
+
+// One streamed sweep of the graph for samples [0, S) of the chunk starting at x.
+hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char *base, const double *x,
+                       int64_t S, int64_t xs, double *out, int32_t *out_exp, hipStream_t st) {
+    void *bufs[2] = {base + w.off_buf0, base + w.off_buf1};
+    uint32_t *maxbits = p == COS_FP32_RESCALED ? reinterpret_cast<uint32_t *>(base + w.off_maxbits) : nullptr;
+    double *partial = reinterpret_cast<double *>(base + w.off_partial);
+    hipError_t err = hipSuccess;
+    if (maxbits)
+        err = launch_fill_u32(maxbits, 0u, static_cast<int64_t>(g.L + 1) * w.S_pad, st);
+    const void *prev = nullptr;  // level 0: the root, value 1
+    for (int l = 1; l <= g.L - 1 && err == hipSuccess; ++l) {
+        void *cur = bufs[(l - 1) & 1];
+        const uint32_t *pm = (maxbits && l >= 2) ? maxbits + static_cast<int64_t>(l - 1) * w.S_pad : nullptr;
+        uint32_t *cm = (maxbits && l <= g.L - 2) ? maxbits + static_cast<int64_t>(l) * w.S_pad : nullptr;
+        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, st);
+        prev = cur;
+    }
+    if (err == hipSuccess)
+        err = launch_final(g, p, prev, w.S_pad, x, S, xs, maxbits, partial, w.final_chunks, out, out_exp, st);
+    return err;
+}
 }  // namespace
 
 extern "C" cos_status cos_evaluate_workspace_size(const cos_graph *h, int64_t S, cos_precision p, uint64_t *bytes) {
@@ -56,42 +103,50 @@ extern "C" cos_status cos_evaluate(const cos_graph *h, const double *x_dev, int6
     if (!x_dev || !out_dev)
         return fail(COS_EINVAL, "cos_evaluate: x or out is NULL");
     const Graph &g = graph_of(h);
-    const Workspace w = plan_workspace(g, S, p);
-    if (w.S_pad * std::max<int64_t>(g.max_width, 1) > (int64_t(1) << 40))
-        return fail(COS_EINVAL, "cos_evaluate: level buffer too large");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g.device)
+        return fail(COS_EINVAL, "cos_evaluate: the current device is not the graph's device");
+    Workspace w = plan_workspace(g, S, p);
+    if (w.fused && !fused_fits(g, p))
+        return fail(COS_EINVAL, "cos_evaluate: the fused plan was requested but the graph does not fit in LDS");
+    if (!w.fused && max_chunk(g, p) < kSamplePad)
+        return fail(COS_EINVAL, "cos_evaluate: a level is too wide for the streamed plan");
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     void *ws = workspace_dev;
     bool owned = false;
     if (ws) {
-        if (workspace_bytes < w.bytes)
-            return fail(COS_EINVAL, "cos_evaluate: workspace smaller than cos_evaluate_workspace_size");
         if (reinterpret_cast<uintptr_t>(ws) % 256)
             return fail(COS_EINVAL, "cos_evaluate: workspace must be 256-byte aligned");
+        if (workspace_bytes < w.bytes) {
+            // a smaller workspace: sweep in smaller sample chunks that fit in it
+            if (w.fused)
+                return fail(COS_EINVAL, "cos_evaluate: workspace smaller than cos_evaluate_workspace_size");
+            int64_t c = w.S_pad - kSamplePad;
+            while (c >= kSamplePad && layout_for_chunk(g, c, p).bytes > workspace_bytes)
+                c -= kSamplePad;
+            if (c < kSamplePad)
+                return fail(COS_EINVAL, "cos_evaluate: workspace too small for even " + std::to_string(kSamplePad) +
+                                            " samples per sweep");
+            w = layout_for_chunk(g, c, p);
+        }
     } else {
         hipError_t err = hipMallocAsync(&ws, w.bytes, st);
         if (err != hipSuccess)
             return hip_fail(err, "hipMallocAsync(workspace)");
         owned = true;
     }
-    char *base = static_cast<char *>(ws);
-    void *bufs[2] = {base + w.off_buf0, base + w.off_buf1};
-    uint32_t *maxbits = p == COS_FP32_RESCALED ? reinterpret_cast<uint32_t *>(base + w.off_maxbits) : nullptr;
-    double *partial = reinterpret_cast<double *>(base + w.off_partial);
 
     hipError_t err = hipSuccess;
-    if (maxbits)
-        err = launch_fill_u32(maxbits, 0u, static_cast<int64_t>(g.L + 1) * w.S_pad, st);
-    const void *prev = nullptr;  // level 0: the root, value 1
-    for (int l = 1; l <= g.L - 1 && err == hipSuccess; ++l) {
-        void *cur = bufs[(l - 1) & 1];
-        const uint32_t *pm = (maxbits && l >= 2) ? maxbits + static_cast<int64_t>(l - 1) * w.S_pad : nullptr;
-        uint32_t *cm = (maxbits && l <= g.L - 2) ? maxbits + static_cast<int64_t>(l) * w.S_pad : nullptr;
-        err = launch_level(g, l, p, prev, cur, w.S_pad, x_dev, S, pm, cm, st);
-        prev = cur;
+    if (w.fused) {
+        err = launch_fused(g, p, x_dev, S, out_dev, out_exp_dev, st);
+    } else {
+        for (int64_t s0 = 0; s0 < S && err == hipSuccess; s0 += w.S_chunk) {
+            const int64_t n = std::min(w.S_chunk, S - s0);
+            err = sweep_chunk(g, p, w, static_cast<char *>(ws), x_dev + s0, n, S, out_dev + s0,
+                              out_exp_dev ? out_exp_dev + s0 : nullptr, st);
+        }
     }
-    if (err == hipSuccess)
-        err = launch_final(g, p, prev, w.S_pad, x_dev, S, maxbits, partial, w.final_chunks, out_dev, out_exp_dev, st);
     if (owned) {
         hipError_t ferr = hipFreeAsync(ws, st);
         if (err == hipSuccess)

@@ -253,8 +253,8 @@ extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const i
 
         // per-level CSR over destinations (global edge indices) and edge records
         std::vector<int32_t> row_ptr(rp);
-        std::vector<EdgeF64> e64(n_edges);
-        std::vector<EdgeF32> e32(n_edges);
+        std::vector<EdgeRec> recs(n_edges + kEdgePad, EdgeRec{});
+        std::vector<LevelDev> ldev(L);
         for (int32_t l = 1; l <= L; ++l) {
             LevelDesc &d = G.levels[l - 1];
             int32_t *r = row_ptr.data() + d.rp_begin;
@@ -274,35 +274,56 @@ extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const i
                 G.max_in_degree = std::max(G.max_in_degree, maxdeg);
             }
             for (int64_t q = d.e_begin; q < d.e_begin + d.n_edges; ++q) {
-                const int32_t s_local = static_cast<int32_t>(G.h_src[q] - sfirst);
-                e64[q] = EdgeF64{G.h_k[3 * q], G.h_k[3 * q + 1], G.h_k[3 * q + 2], G.h_b[q], G.h_a[q], s_local, 0};
-                e32[q] = EdgeF32{static_cast<float>(G.h_k[3 * q]), static_cast<float>(G.h_k[3 * q + 1]),
-                                 static_cast<float>(G.h_k[3 * q + 2]), static_cast<float>(G.h_b[q]),
-                                 static_cast<float>(G.h_a[q]), s_local, 0, 0};
+                const double b = G.h_b[q], k0 = G.h_k[3 * q], k1 = G.h_k[3 * q + 1], k2 = G.h_k[3 * q + 2];
+                EdgeRec &rec = recs[q];
+                rec.c0 = 1.0 + b * (k0 * k0 + k1 * k1 + k2 * k2);
+                rec.cb = b;
+                rec.g0 = -2.0 * b * k0;
+                rec.g1 = -2.0 * b * k1;
+                rec.g2 = -2.0 * b * k2;
+                rec.a = G.h_a[q];
+                rec.src = static_cast<int32_t>(G.h_src[q] - sfirst);
+                rec.a32 = static_cast<float>(G.h_a[q]);
+                rec.row_end = 0;
+                rec.zero_rows = 0;
             }
+            // row boundaries inside the edge stream: the last edge of every
+            // non-empty row, and how many empty rows follow it
+            for (int64_t j = 0; j < d.w_dst; ++j) {
+                if (r[j + 1] == r[j])
+                    continue;
+                EdgeRec &last = recs[r[j + 1] - 1];
+                last.row_end = 1;
+                int64_t z = j + 1;
+                while (z < d.w_dst && r[z + 1] == r[z])
+                    ++z;
+                last.zero_rows = static_cast<int32_t>(z - (j + 1));
+            }
+            ldev[l - 1] = LevelDev{static_cast<int32_t>(d.w_dst), static_cast<int32_t>(d.rp_begin),
+                                   static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges)};
         }
 
-        // one device allocation: row_ptr | e64 | e32
+        // one device allocation: row_ptr | edge records | level table
         const size_t off_rp = 0;
-        const size_t off_64 = round_up(rp * sizeof(int32_t), 256);
-        const size_t off_32 = off_64 + round_up(n_edges * sizeof(EdgeF64), 256);
-        const size_t total = off_32 + round_up(n_edges * sizeof(EdgeF32), 256);
+        const size_t off_rec = round_up(rp * sizeof(int32_t), 256);
+        const size_t off_lev = off_rec + round_up((n_edges + kEdgePad) * sizeof(EdgeRec), 256);
+        const size_t total = off_lev + round_up(L * sizeof(LevelDev), 256);
         hipError_t err = hipGetDevice(&G.device);
         if (err != hipSuccess)
             return hip_fail(err, "hipGetDevice");
-        err = hipMalloc(&G.d_base, std::max<size_t>(total, 256));
+        err = hipMalloc(&G.d_base, total);
         if (err != hipSuccess)
             return hip_fail(err, "hipMalloc(graph)");
-        G.d_bytes = std::max<size_t>(total, 256);
+        G.d_bytes = total;
         char *base = static_cast<char *>(G.d_base);
         G.d_row_ptr = reinterpret_cast<int32_t *>(base + off_rp);
-        G.d_e64 = reinterpret_cast<EdgeF64 *>(base + off_64);
-        G.d_e32 = reinterpret_cast<EdgeF32 *>(base + off_32);
+        G.d_edges = reinterpret_cast<EdgeRec *>(base + off_rec);
+        G.d_levels = reinterpret_cast<LevelDev *>(base + off_lev);
         err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
-        if (err == hipSuccess && n_edges)
-            err = hipMemcpy(G.d_e64, e64.data(), n_edges * sizeof(EdgeF64), hipMemcpyHostToDevice);
-        if (err == hipSuccess && n_edges)
-            err = hipMemcpy(G.d_e32, e32.data(), n_edges * sizeof(EdgeF32), hipMemcpyHostToDevice);
+        if (err == hipSuccess)
+            err = hipMemcpy(G.d_edges, recs.data(), recs.size() * sizeof(EdgeRec), hipMemcpyHostToDevice);
+        if (err == hipSuccess)
+            err = hipMemcpy(G.d_levels, ldev.data(), L * sizeof(LevelDev), hipMemcpyHostToDevice);
         if (err != hipSuccess) {
             (void)hipFree(G.d_base);
             return hip_fail(err, "hipMemcpy(graph)");
@@ -321,13 +342,23 @@ extern "C" cos_status cos_graph_get_info(const cos_graph *h, cos_graph_info *inf
         return fail(COS_EINVAL, "cos_graph_get_info: NULL argument");
     const Graph &G = h->g;
     info->L = G.L;
-    info->reserved = 0;
+    info->fused_mask = (fused_fits(G, COS_FP64) ? 1 : 0) | (fused_fits(G, COS_FP32_RESCALED) ? 2 : 0) |
+                       (fused_fits(G, COS_FP32) ? 4 : 0);
     info->n_nodes = G.n_nodes;
     info->n_edges = G.n_edges;
     info->max_width = G.max_width;
     info->max_in_degree = G.max_in_degree;
     info->final_in_degree = G.levels.back().n_edges;
     info->device_bytes = G.d_bytes;
+    return COS_OK;
+}
+
+extern "C" cos_status cos_graph_set_path(cos_graph *h, cos_path path) {
+    if (!h)
+        return fail(COS_EINVAL, "cos_graph_set_path: graph is NULL");
+    if (path != COS_PATH_AUTO && path != COS_PATH_STREAMED && path != COS_PATH_FUSED)
+        return fail(COS_EINVAL, "cos_graph_set_path: unknown path");
+    h->g.path = path;
     return COS_OK;
 }
 

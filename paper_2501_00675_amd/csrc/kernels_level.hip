@@ -1,4 +1,5 @@
-// Level-sweep kernels for gfx950.
+// Level-sweep kernels for gfx950: one launch per interior level (streamed
+// through HBM) and the final-node split reduction.
 //
 // One launch per interior edge level l = 1..L-1 computes, for every node j of
 // level l and every sample s,
@@ -21,116 +22,161 @@
 //
 // The final node, whose in-degree is the whole of level L-1, is reduced in
 // binary64 by a two-pass split reduction with a fixed combination order.
-#include "cos_internal.h"
+#include "kernels_common.h"
 
 namespace cosdag {
 namespace {
 
-template <typename T>
-struct EdgeOf;
-template <>
-struct EdgeOf<double> {
-    using type = EdgeF64;
-};
-template <>
-struct EdgeOf<float> {
-    using type = EdgeF32;
-};
-
-// ilogb of a non-negative binary32 given by its bit pattern; 0, inf and NaN
-// give 0 (no rescale).
-__device__ __forceinline__ int ilogb_bits(uint32_t u) {
-    if (u == 0u || u >= 0x7f800000u)
-        return 0;
-    const uint32_t ex = u >> 23;
-    if (ex)
-        return static_cast<int>(ex) - 127;
-    return (31 - __clz(u)) - 149;  // subnormal
+// Block -> (sample tile, row group).
+//
+// xcd_group = 1: workgroups are dispatched round-robin over the 8 XCDs (block
+// b runs on XCD b % 8), each XCD with its own L2.  All row groups of one
+// sample tile go to the same XCD, so the tile's source rows -- read by ~d
+// destinations each -- are fetched into one L2 only.  Used when a tile's slice
+// of the previous level fits in L2.  Grids are padded to a multiple of 8
+// tiles; blocks of a padding tile return at once.
+// xcd_group = 0: tile-major order, so the whole GPU works on one tile at a
+// time and the tile's slice of the previous level stays in the memory-side
+// Infinity Cache while every XCD gathers from it.
+__device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group, int &tile, int &rg) {
+    if (xcd_group) {
+        const int xcd = static_cast<int>(blockIdx.x % kXcds);
+        const int local = static_cast<int>(blockIdx.x / kXcds);
+        const int t = local / n_rg;
+        rg = local - t * n_rg;
+        tile = t * kXcds + xcd;
+    } else {
+        tile = static_cast<int>(blockIdx.x) / n_rg;
+        rg = static_cast<int>(blockIdx.x) - tile * n_rg;
+    }
+    return tile < n_tiles;
 }
 
-__device__ __forceinline__ double edge_factor(const EdgeF64 &e, double x0, double x1, double x2) {
-    const double d0 = x0 - e.k0, d1 = x1 - e.k1, d2 = x2 - e.k2;
-    const double r2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
-    return e.a / __builtin_fma(e.b, r2, 1.0);
-}
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-__device__ __forceinline__ float edge_factor(const EdgeF32 &e, float x0, float x1, float x2) {
-    const float d0 = x0 - e.k0, d1 = x1 - e.k1, d2 = x2 - e.k2;
-    const float r2 = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
-    // v_rcp_f32 (1 ulp): the denominator is >= 1, far from the rcp's edge cases
-    return e.a * __builtin_amdgcn_rcpf(__builtin_fmaf(e.b, r2, 1.0f));
-}
+// Edges fetched per step of a stream: kEdgePad zeroed records follow the last
+// edge on the device, so a full chunk can always be read.
+constexpr int kChunk = kEdgePad;
 
-__device__ __forceinline__ uint32_t abs_bits(float v) { return __float_as_uint(v) & 0x7fffffffu; }
-
-// Interior level.  Workgroup = 4 waves; the group owns 4*ROWS consecutive
-// destination rows (wave w takes rows w, w+4, ...) for one tile of 64*K
-// samples; lane i of a wave handles samples tile*64K + i + 64m, m < K, so every
-// load and store instruction covers 64 consecutive values of one row.
+// Interior level.  Workgroup = 4 waves; wave w owns ROWS consecutive
+// destination rows, so its edges form one contiguous stream in canonical
+// order, all for one tile of 64*K samples (lane i handles samples
+// tile*64K + i + 64m, m < K: every load and store covers 64 consecutive values
+// of one row).  The stream is walked in chunks of four edges: the four records
+// are fetched together (one scalar wait), the 4*K source values are requested
+// together (one vector wait), then the four factors are accumulated.  A row is
+// stored when its last edge (flagged in the record) has been added; rows
+// without in-edges are stored as zeros.
 //
 // FROM_ROOT: level 1, whose only source is the root (value 1).
 // RESCALE:   binary32 with per-(level, sample) power-of-two scaling: the
 //            accumulated sum is multiplied by 2^-e_{l-1}[s], e_{l-1}[s] being
-//            ilogb of the largest |value| of level l-1 for sample s (exact
-//            scaling); the largest |value| of this level is folded into
-//            cur_max[s] with an integer max over bit patterns (order-free).
+//            ilogb of the largest |value| of level l-1 for sample s (exact);
+//            the largest |value| of this level is folded into cur_max[s] by an
+//            integer max over bit patterns (order-free, hence deterministic).
 template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE>
 __global__ __launch_bounds__(kBlock) void level_gather_kernel(
-    const int32_t *__restrict__ row_ptr, const typename EdgeOf<T>::type *__restrict__ edges,
-    int32_t w_dst, int32_t n_row_groups, const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
-    const double *__restrict__ x, int64_t S, const uint32_t *__restrict__ prev_max,
+    const int32_t *__restrict__ row_ptr, const EdgeRec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
+    int32_t n_tiles, int32_t xcd_group, const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
+    const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
     uint32_t *__restrict__ cur_max) {
-    using Edge = typename EdgeOf<T>::type;
+    int tile, rg;
+    if (!block_tile(n_rg, n_tiles, xcd_group, tile, rg))
+        return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tile = blockIdx.x / n_row_groups;
-    const int rg = blockIdx.x - tile * n_row_groups;
-    const int64_t s0 = static_cast<int64_t>(tile) * (kWave * K) + lane;
+    const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
 
-    T x0[K], x1[K], x2[K];
+    double x0[K], x1[K], x2[K], q[K];
     int esh[K];
     uint32_t lmax[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-        const int64_t s = s0 + kWave * m;
+        const int64_t s = tbase + lane + kWave * m;
         const bool in = s < S;
-        x0[m] = in ? static_cast<T>(x[s]) : T(0);
-        x1[m] = in ? static_cast<T>(x[S + s]) : T(0);
-        x2[m] = in ? static_cast<T>(x[2 * S + s]) : T(0);
+        x0[m] = in ? x[s] : 0.0;
+        x1[m] = in ? x[xs + s] : 0.0;
+        x2[m] = in ? x[2 * xs + s] : 0.0;
+        q[m] = __builtin_fma(x2[m], x2[m], __builtin_fma(x1[m], x1[m], x0[m] * x0[m]));
         esh[m] = (RESCALE && prev_max) ? ilogb_bits(prev_max[s]) : 0;
         lmax[m] = 0u;
     }
 
-    const int row0 = rg * (4 * ROWS);
-#pragma unroll 1
-    for (int r = 0; r < ROWS; ++r) {
-        const int j = row0 + r * 4 + wave;
-        if (j >= w_dst)
-            break;
-        const int e0 = row_ptr[j], e1 = row_ptr[j + 1];
-        T acc[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m)
-            acc[m] = T(0);
-#pragma unroll 2
-        for (int e = e0; e < e1; ++e) {
-            const Edge ed = edges[e];
-            const T *srow = prev + static_cast<int64_t>(ed.src) * ld + s0;
-#pragma unroll
-            for (int m = 0; m < K; ++m) {
-                const T v = FROM_ROOT ? T(1) : srow[kWave * m];
-                acc[m] = fma(edge_factor(ed, x0[m], x1[m], x2[m]), v, acc[m]);
-            }
-        }
-        T *crow = cur + static_cast<int64_t>(j) * ld + s0;
+    T *const out_base = cur + tbase + lane;
+    auto store_row = [&](int j, const T *acc) {
+        T *crow = out_base + static_cast<int64_t>(j) * ld;
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             T z = acc[m];
             if constexpr (RESCALE) {
-                z = ldexpf(z, -esh[m]);
+                z = scale_pow2(z, esh[m]);
                 lmax[m] = max(lmax[m], abs_bits(z));
             }
             crow[kWave * m] = z;
+        }
+    };
+
+    const int jbeg = min(rg * (4 * ROWS) + wave * ROWS, w_dst);
+    const int jend = min(jbeg + ROWS, w_dst);
+    if (jbeg < jend) {
+        int j = jbeg;
+        int e = row_ptr[jbeg];
+        const int e_end = row_ptr[jend];
+        T acc[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            acc[m] = T(0);
+        // rows without in-edges at the start of this wave's range
+        while (j < jend && row_ptr[j + 1] == e) {
+            store_row(j, acc);
+            ++j;
+        }
+        const EdgeRec *rec = edges + e;
+        // the tile's column block of the previous level; a source row is
+        // reached by a 32-bit byte offset (level buffers are < 2 GiB, which the
+        // planner guarantees by splitting S) and each lane adds its own column
+        const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
+        const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(T));
+        const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(T));
+        while (e < e_end) {
+            const int n = min(kChunk, e_end - e);
+            EdgeRec r[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                r[u] = rec[u];  // past e_end: the next edges or the zeroed pad, never used
+            // all 4*K source values of the chunk are requested before any is
+            // used; records past the end name rows inside the level buffer
+            // (src < widest level), so the unused reads stay in bounds
+            T v[kChunk][K];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    v[u][m] = FROM_ROOT ? T(1) : *reinterpret_cast<const T *>(row + m * kWave * sizeof(T));
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                if (u < n) {
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        acc[m] = fma_t(edge_factor<T>(r[u], x0[m], x1[m], x2[m], q[m]), v[u][m], acc[m]);
+                    if (r[u].row_end) {
+                        store_row(j, acc);
+                        ++j;
+#pragma unroll
+                        for (int m = 0; m < K; ++m)
+                            acc[m] = T(0);
+                        for (int z = 0; z < r[u].zero_rows && j < jend; ++z) {
+                            store_row(j, acc);
+                            ++j;
+                        }
+                    }
+                }
+            }
+            rec += n;
+            e += n;
         }
     }
 
@@ -144,58 +190,70 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
             for (int i = threadIdx.x; i < kWave * K; i += kBlock) {
                 const uint32_t v = max(max(red[0][i], red[1][i]), max(red[2][i], red[3][i]));
                 if (v)
-                    atomicMax(cur_max + static_cast<int64_t>(tile) * (kWave * K) + i, v);
+                    atomicMax(cur_max + tbase + i, v);
             }
         }
     }
 }
 
-// Final node, pass 1: block (chunk c, sample tile t) sums the edges of chunk c
-// in binary64; wave w takes the w-th quarter of the chunk; the four wave sums
-// are added in a fixed order and written to partial[c][s].
+// Final node, pass 1: block (sample tile, chunk c) sums the edges of chunk c
+// (kFinalChunk edges) in binary64; wave w takes the w-th quarter of the chunk;
+// the four wave sums are added as ((q0 + q1) + q2) + q3 into partial[c][s].
 template <typename TV, int K, bool FROM_ROOT>
 __global__ __launch_bounds__(kBlock) void final_partial_kernel(
-    const EdgeF64 *__restrict__ edges, int32_t n_edges, int32_t chunk, int32_t n_chunks,
-    const TV *__restrict__ prev, int64_t ld, const double *__restrict__ x, int64_t S,
-    double *__restrict__ partial) {
+    const EdgeRec *__restrict__ edges, int32_t n_edges, int32_t n_chunks, const TV *__restrict__ prev, int64_t ld,
+    const double *__restrict__ x, int64_t S, int64_t xs, double *__restrict__ partial) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = blockIdx.x / n_chunks;
     const int c = blockIdx.x - tile * n_chunks;
-    const int64_t s0 = static_cast<int64_t>(tile) * (kWave * K) + lane;
-    double x0[K], x1[K], x2[K], acc[K];
+    const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
+    double x0[K], x1[K], x2[K], q[K], acc[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-        const int64_t s = s0 + kWave * m;
+        const int64_t s = tbase + lane + kWave * m;
         const bool in = s < S;
         x0[m] = in ? x[s] : 0.0;
-        x1[m] = in ? x[S + s] : 0.0;
-        x2[m] = in ? x[2 * S + s] : 0.0;
+        x1[m] = in ? x[xs + s] : 0.0;
+        x2[m] = in ? x[2 * xs + s] : 0.0;
+        q[m] = __builtin_fma(x2[m], x2[m], __builtin_fma(x1[m], x1[m], x0[m] * x0[m]));
         acc[m] = 0.0;
     }
-    const int q = (chunk + 3) / 4;
-    const int c_end = min((c + 1) * chunk, n_edges);
-    const int e_lo = min(c * chunk + wave * q, c_end);
-    const int e_hi = min(e_lo + q, c_end);
-#pragma unroll 2
-    for (int e = e_lo; e < e_hi; ++e) {
-        const EdgeF64 ed = edges[e];
-        const TV *srow = prev + static_cast<int64_t>(ed.src) * ld + s0;
+    constexpr int kQuarter = kFinalChunk / 4;
+    const int c_end = min((c + 1) * kFinalChunk, n_edges);
+    const int e_lo = min(c * kFinalChunk + wave * kQuarter, c_end);
+    const int e_hi = min(e_lo + kQuarter, c_end);
+    const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
+    const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(TV));
+    const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(TV));
+    for (int e = e_lo; e < e_hi; e += kChunk) {
+        const int n = min(kChunk, e_hi - e);
+        EdgeRec r[kChunk];
 #pragma unroll
-        for (int m = 0; m < K; ++m) {
-            const double v = FROM_ROOT ? 1.0 : static_cast<double>(srow[kWave * m]);
-            acc[m] = __builtin_fma(edge_factor(ed, x0[m], x1[m], x2[m]), v, acc[m]);
+        for (int u = 0; u < kChunk; ++u)
+            r[u] = edges[e + u];  // the edge array is padded: full chunks are always readable
+        double v[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                v[u][m] = FROM_ROOT ? 1.0 : static_cast<double>(*reinterpret_cast<const TV *>(row + m * kWave * sizeof(TV)));
         }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            if (u < n)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    acc[m] = __builtin_fma(edge_factor64(r[u], x0[m], x1[m], x2[m], q[m]), v[u][m], acc[m]);
     }
     __shared__ double red[4][kWave * K];
 #pragma unroll
     for (int m = 0; m < K; ++m)
         red[wave][lane + kWave * m] = acc[m];
     __syncthreads();
-    const int64_t S_pad = ld;
     for (int i = threadIdx.x; i < kWave * K; i += kBlock)
-        partial[static_cast<int64_t>(c) * S_pad + static_cast<int64_t>(tile) * (kWave * K) + i] =
-            ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+        partial[static_cast<int64_t>(c) * ld + tbase + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
 // Final node, pass 2: out[s] = sum over chunks in ascending order, then the
@@ -228,38 +286,36 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t *__restrict__
         p[i] = v;
 }
 
-constexpr int kRows = 4;      // rows per wave in the interior-level kernel
-constexpr int kK = 2;         // samples per lane
-constexpr int kFinalChunk = 256;
+constexpr int kRows = 8;      // consecutive rows per wave in the interior-level kernel
+constexpr int kK = 4;         // samples per lane (interior levels)
+constexpr int kKFinal = 2;    // samples per lane (final node)
+constexpr int64_t kL2Slice = 1 << 20;  // a tile slice up to this size is kept in one XCD's L2
 
 template <typename T, bool RESCALE>
 hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
-                          int64_t S, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
+                          int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
     const LevelDesc &d = g.levels[l - 1];
     const int32_t rows_per_group = 4 * kRows;
-    const int32_t n_rg = static_cast<int32_t>((d.w_dst + rows_per_group - 1) / rows_per_group);
+    const int64_t n_rg = (d.w_dst + rows_per_group - 1) / rows_per_group;
     const int64_t n_tiles = ld / (kWave * kK);
-    const int64_t grid = n_tiles * n_rg;
+    const int32_t xcd_group = d.w_src * kWave * kK * static_cast<int64_t>(sizeof(T)) <= kL2Slice ? 1 : 0;
+    const int64_t grid = (xcd_group ? round_up(n_tiles, kXcds) : n_tiles) * n_rg;
     if (grid <= 0)
         return hipSuccess;
     if (grid > INT32_MAX)
         return hipErrorInvalidConfiguration;
     const int32_t *rp = g.d_row_ptr + d.rp_begin;
-    const auto *edges = [&]() {
-        if constexpr (sizeof(T) == 8)
-            return g.d_e64;
-        else
-            return g.d_e32;
-    }();
     TimedLaunch tl(KK_LEVEL, s);
     if (prev == nullptr)
         hipLaunchKernelGGL((level_gather_kernel<T, kK, kRows, true, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
-                           edges, static_cast<int32_t>(d.w_dst), n_rg, nullptr, static_cast<T *>(cur), ld, x, S,
+                           g.d_edges, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
+                           static_cast<int32_t>(n_tiles), xcd_group, nullptr, static_cast<T *>(cur), ld, x, S, xs,
                            prev_max, cur_max);
     else
         hipLaunchKernelGGL((level_gather_kernel<T, kK, kRows, false, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
-                           edges, static_cast<int32_t>(d.w_dst), n_rg, static_cast<const T *>(prev),
-                           static_cast<T *>(cur), ld, x, S, prev_max, cur_max);
+                           g.d_edges, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
+                           static_cast<int32_t>(n_tiles), xcd_group, static_cast<const T *>(prev),
+                           static_cast<T *>(cur), ld, x, S, xs, prev_max, cur_max);
     return hipGetLastError();
 }
 
@@ -270,37 +326,38 @@ int32_t final_chunk_count(int64_t final_in_degree) {
 }
 
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
-                        const double *x, int64_t S, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
+                        const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
+                        hipStream_t s) {
     switch (p) {
     case COS_FP64:
-        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, nullptr, nullptr, s);
+        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, s);
     case COS_FP32_RESCALED:
-        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, prev_max, cur_max, s);
+        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
     case COS_FP32:
-        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, nullptr, nullptr, s);
+        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld, const double *x, int64_t S,
-                        const uint32_t *maxbits, double *partial, int32_t chunks, double *out, int32_t *out_exp,
-                        hipStream_t s) {
+                        int64_t xs, const uint32_t *maxbits, double *partial, int32_t chunks, double *out,
+                        int32_t *out_exp, hipStream_t s) {
     const LevelDesc &d = g.levels[g.L - 1];
-    const int64_t n_tiles = ld / (kWave * kK);
-    const EdgeF64 *edges = g.d_e64 + d.e_begin;
+    const int64_t n_tiles = ld / (kWave * kKFinal);
+    const EdgeRec *edges = g.d_edges + d.e_begin;
     const int32_t ne = static_cast<int32_t>(d.n_edges);
     {
         TimedLaunch tl(KK_FINAL_PARTIAL, s);
         const dim3 grid(static_cast<unsigned>(n_tiles * chunks));
         if (prev == nullptr)
-            hipLaunchKernelGGL((final_partial_kernel<double, kK, true>), grid, dim3(kBlock), 0, s, edges, ne,
-                               kFinalChunk, chunks, static_cast<const double *>(nullptr), ld, x, S, partial);
+            hipLaunchKernelGGL((final_partial_kernel<double, kKFinal, true>), grid, dim3(kBlock), 0, s, edges, ne,
+                               chunks, static_cast<const double *>(nullptr), ld, x, S, xs, partial);
         else if (p == COS_FP64)
-            hipLaunchKernelGGL((final_partial_kernel<double, kK, false>), grid, dim3(kBlock), 0, s, edges, ne,
-                               kFinalChunk, chunks, static_cast<const double *>(prev), ld, x, S, partial);
+            hipLaunchKernelGGL((final_partial_kernel<double, kKFinal, false>), grid, dim3(kBlock), 0, s, edges, ne,
+                               chunks, static_cast<const double *>(prev), ld, x, S, xs, partial);
         else
-            hipLaunchKernelGGL((final_partial_kernel<float, kK, false>), grid, dim3(kBlock), 0, s, edges, ne,
-                               kFinalChunk, chunks, static_cast<const float *>(prev), ld, x, S, partial);
+            hipLaunchKernelGGL((final_partial_kernel<float, kKFinal, false>), grid, dim3(kBlock), 0, s, edges, ne,
+                               chunks, static_cast<const float *>(prev), ld, x, S, xs, partial);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess)
             return err;

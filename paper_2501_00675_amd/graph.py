@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import KINDS, LIB, PRECISIONS, GraphInfo, check
+from ._lib import KINDS, LIB, PATHS, PRECISIONS, GraphInfo, check
 
 
 def _c(a, dtype):
@@ -51,7 +51,12 @@ class Graph:
     def info(self) -> dict:
         gi = GraphInfo()
         check(LIB.cos_graph_get_info(self.handle, ctypes.byref(gi)), "cos_graph_get_info")
-        return {f: getattr(gi, f) for f, _ in GraphInfo._fields_ if f != "reserved"}
+        return {f: getattr(gi, f) for f, _ in GraphInfo._fields_}
+
+    def set_path(self, path: str = "auto") -> "Graph":
+        """Kernel plan for later evaluations: 'auto', 'streamed' or 'fused' (cos_graph_set_path)."""
+        check(LIB.cos_graph_set_path(self.handle, PATHS[path]), "cos_graph_set_path")
+        return self
 
     def export(self) -> dict:
         E = self.info()["n_edges"]
@@ -82,11 +87,9 @@ class Graph:
         if out_exp is not None and not (out_exp.is_cuda and out_exp.dtype == torch.int32
                                         and out_exp.numel() >= S and out_exp.is_contiguous()):
             raise ValueError("out_exp must be a contiguous int32 CUDA tensor with >= S elements")
-        need = self.workspace_bytes(S, precision)
         if workspace is None:
-            workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
-        if workspace.numel() * workspace.element_size() < need:
-            raise ValueError(f"workspace needs {need} bytes")
+            workspace = torch.empty(self.workspace_bytes(S, precision), dtype=torch.uint8, device=x.device)
+        # a workspace smaller than workspace_bytes(S) makes the library sweep in sample chunks
         st = stream if stream is not None else torch.cuda.current_stream(x.device)
         check(LIB.cos_evaluate(self.handle, x.data_ptr(), S, PRECISIONS[precision], out.data_ptr(),
                                out_exp.data_ptr() if out_exp is not None else None, workspace.data_ptr(),

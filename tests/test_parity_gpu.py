@@ -49,12 +49,40 @@ def test_tiny_parity(P, precision):
 
 @pytest.mark.parametrize("S", [1, 2, 63, 64, 65, 127, 255, 257, 1000])
 @pytest.mark.parametrize("precision", ["fp64", "fp32r"])
-def test_ragged_sample_counts(P, S, precision):
+@pytest.mark.parametrize("path", ["fused", "streamed"])
+def test_ragged_sample_counts(P, S, precision, path):
     g, x = make_config("mid", S=S, width=40, L=6)
-    say(f"ragged {precision} S={S}")
-    y = gpu_eval(graph(P, g), x, precision)
+    say(f"ragged {precision} {path} S={S}")
+    y = gpu_eval(graph(P, g).set_path(path), x, precision)
     V, Q = oracle_ref(g, x)
     assert_parity(y, V, Q, precision, f"ragged S={S}")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("name,S,over", [("tiny", 1024, {}), ("mid", 1000, {}), ("mid", 4096, {}),
+                                         ("mid", 777, dict(width=300, L=5, degree=7))])
+def test_fused_and_streamed_bit_identical(P, precision, name, S, over):
+    g, x = make_config(name, S=S, **over)
+    G = graph(P, g)
+    code = {"fp64": 0, "fp32r": 1, "fp32": 2}[precision]
+    if not (G.info()["fused_mask"] >> code) & 1:
+        pytest.skip("graph does not fit the fused plan at this precision")
+    say(f"fused vs streamed {name} {precision} S={S} {over}")
+    yf = gpu_eval(G.set_path("fused"), x, precision)
+    ys = gpu_eval(G.set_path("streamed"), x, precision)
+    assert np.array_equal(yf.view(np.uint64), ys.view(np.uint64))
+    V, Q = oracle_ref(g, x)
+    assert_parity(yf, V, Q, precision, f"{name} fused")
+
+
+def test_fused_plan_rejected_when_too_wide(P):
+    g, x = make_config("precision", S=64)
+    G = graph(P, g)
+    assert G.info()["fused_mask"] == 0
+    G.set_path("fused")
+    with pytest.raises(P.CosError) as ei:
+        gpu_eval(G, x, "fp64")
+    assert ei.value.status == -1
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
@@ -235,16 +263,33 @@ def test_workspace_checks(P):
     g, x = make_config("tiny", S=100)
     G = graph(P, g)
     xd = to_dev(x)
+    G.set_path("streamed")
     need = G.workspace_bytes(100, "fp64")
     ws = torch.empty(need + 512, dtype=torch.uint8, device=xd.device)
-    with pytest.raises(ValueError):
-        G.evaluate(xd, "fp64", workspace=ws[: need - 8])
+    with pytest.raises(P.CosError):
+        G.evaluate(xd, "fp64", workspace=ws[: need - 8])  # not even one 256-sample sweep fits
     with pytest.raises(P.CosError):
         G.evaluate(xd, "fp64", workspace=ws[8:])  # misaligned
     y = G.evaluate(xd, "fp64", workspace=ws)
     torch.cuda.synchronize()
     V, Q = oracle_ref(g, x)
     assert_parity(y.cpu().numpy(), V, Q, "fp64", "workspace")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_small_workspace_sweeps_in_chunks_bit_identical(P, precision):
+    # a workspace sized for 1000 samples evaluates 4100 samples in 5 sweeps (ragged last one)
+    g, x = make_config("mid", S=4100, width=96, L=7)
+    G = graph(P, g).set_path("streamed")
+    xd = to_dev(x)
+    full = G.evaluate(xd, precision)
+    small = torch.empty(G.workspace_bytes(1000, precision), dtype=torch.uint8, device=xd.device)
+    assert small.numel() < G.workspace_bytes(4100, precision)
+    chunked = G.evaluate(xd, precision, workspace=small)
+    torch.cuda.synchronize()
+    assert np.array_equal(full.cpu().numpy(), chunked.cpu().numpy())
+    V, Q = oracle_ref(g, x)
+    assert_parity(chunked.cpu().numpy(), V, Q, precision, "chunked")
 
 
 def test_side_stream(P):
@@ -268,12 +313,15 @@ def test_timing_probe_counts_launches(P):
         P.timing_read(kind)
     P.timing_enable(True)
     try:
-        G.evaluate(xd, "fp64")
+        G.set_path("streamed").evaluate(xd, "fp64")
         torch.cuda.synchronize()
         ms_l, n_l = P.timing_read("level")
-        ms_f, n_f = P.timing_read("fused")
         ms_p, n_p = P.timing_read("final_partial")
+        G.set_path("fused").evaluate(xd, "fp64")
+        torch.cuda.synchronize()
+        ms_f, n_f = P.timing_read("fused")
     finally:
         P.timing_enable(False)
+    assert n_l == g.L - 1 and ms_l > 0
     assert n_p == 1 and ms_p > 0
-    assert n_l + n_f >= 1 and ms_l + ms_f > 0
+    assert n_f == 1 and ms_f > 0
