@@ -13,6 +13,7 @@ error of the GPU results.
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import platform
@@ -47,7 +48,9 @@ def level_bytes(g, S_pad: int, precision: str) -> list:
     rows once, write this level's rows once, read the edge records and row
     pointers once, read x once (S samples, 3 x float64)."""
     B = 8 if precision == "fp64" else 4
-    rec = 48 if precision == "fp64" else 32
+    # record fields a launch needs: src (4 B), the five denominator coefficients (binary64) and a
+    # (binary64 for FP64, binary32 for the FP32 paths)
+    rec = 4 + 5 * 8 + (8 if precision == "fp64" else 4)
     out = []
     for l in range(1, g.L):
         w_prev = 0 if l == 1 else int(g.widths[l - 1])  # level 1 reads the root's constant 1
@@ -133,7 +136,7 @@ def run_timed(P, G, xd, precision, steps, warmup):
     return ms, kern, out
 
 
-def roofline(g, S_pad, precision, kern, steps):
+def roofline(g, S_pad, precision, kern, steps, workload):
     """Roofline of the dominant kernel class, from its live HIP-event timings."""
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     if dom == "level":
@@ -169,8 +172,27 @@ def roofline(g, S_pad, precision, kern, steps):
              "other_term": {"hbm_gbs_compulsory": hbm_bytes / t_launch / 1e9}}
     else:
         r = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "kernel": dom}
-    r["traffic"] = None
+    r["traffic"] = profiled_traffic(r.get("kernel"), workload, precision)
     return r
+
+
+def profiled_traffic(kernel, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summaries (FETCH_SIZE and WRITE_SIZE in KiB
+    per dispatch, scaled by the factors a plain copy kernel gives), or None when no summary exists for this
+    kernel and workload or the library was rebuilt since the counters were taken."""
+    import paper_2501_00675_amd as P
+
+    build = P.LIB.cos_build_id().decode()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("pmc:"):
+                continue
+            kv = dict(item.split("=", 1) for item in line[4:].split())
+            if (kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("precision") == precision
+                    and kv.get("build_id") == build):
+                return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"])
+                                 + float(kv["write_kib"]) * float(kv["write_scale"]))
+    return None
 
 
 def calibrate_copy(steps: int, nbytes: int = 1 << 30):
@@ -240,14 +262,14 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload], "L": g.L, "edges": E, "nodes": g.n_nodes, "S": S,
                    "precision": args.precision, "seed": g.meta.get("seed")},
         "kernels": kern,
-        "roofline": roofline(g, S_pad, args.precision, kern, args.steps),
+        "roofline": roofline(g, S_pad, args.precision, kern, args.steps, args.workload),
     }
     variants = {}
     for pv in [v for v in args.variants.split(",") if v and v != args.precision]:
         print(f"# variant {pv}", file=sys.stderr, flush=True)
         msv, kv, outv = run_timed(P, G, xd, pv, args.steps, args.warmup)
         variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "kernels": kv,
-                        "roofline": roofline(g, S_pad, pv, kv, args.steps), "_y": outv.cpu().numpy()}
+                        "roofline": roofline(g, S_pad, pv, kv, args.steps, args.workload), "_y": outv.cpu().numpy()}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         idx = np.unique(np.concatenate([[0, S - 1], np.random.default_rng(0).choice(S, min(S, 1024) - 2,

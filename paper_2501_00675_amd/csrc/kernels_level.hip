@@ -22,7 +22,7 @@
 //
 // The final node, whose in-degree is the whole of level L-1, is reduced in
 // binary64 by a two-pass split reduction with a fixed combination order.
-#include "kernels_common.h"
+#include "sweep_device.h"
 
 namespace cosdag {
 namespace {
@@ -52,29 +52,13 @@ __device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group,
     return tile < n_tiles;
 }
 
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// Edges fetched per step of a stream: kEdgePad zeroed records follow the last
-// edge on the device, so a full chunk can always be read.
-constexpr int kChunk = kEdgePad;
-
 // Interior level.  Workgroup = 4 waves; wave w owns ROWS consecutive
-// destination rows, so its edges form one contiguous stream in canonical
-// order, all for one tile of 64*K samples (lane i handles samples
-// tile*64K + i + 64m, m < K: every load and store covers 64 consecutive values
-// of one row).  The stream is walked in chunks of four edges: the four records
-// are fetched together (one scalar wait), the 4*K source values are requested
-// together (one vector wait), then the four factors are accumulated.  A row is
-// stored when its last edge (flagged in the record) has been added; rows
-// without in-edges are stored as zeros.
-//
-// FROM_ROOT: level 1, whose only source is the root (value 1).
-// RESCALE:   binary32 with per-(level, sample) power-of-two scaling: the
-//            accumulated sum is multiplied by 2^-e_{l-1}[s], e_{l-1}[s] being
-//            ilogb of the largest |value| of level l-1 for sample s (exact);
-//            the largest |value| of this level is folded into cur_max[s] by an
-//            integer max over bit patterns (order-free, hence deterministic).
+// destination rows of the group's row range, for one tile of 64*K samples
+// (lane i handles samples tile*64K + i + 64m, m < K: every load and store
+// covers 64 consecutive values of one row); see level_wave_rows.
+// RESCALE: the rows are scaled by 2^-e_{l-1}[s], e_{l-1}[s] = ilogb of the
+// largest |value| of level l-1 for sample s (read from prev_max), and the
+// largest |value| of this level is folded into cur_max[s].
 template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE>
 __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     const int32_t *__restrict__ row_ptr, const EdgeRec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
@@ -87,111 +71,23 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
-
-    double x0[K], x1[K], x2[K], q[K];
+    LaneSamples<K> smp;
+    smp.load(x, S, xs, tbase, lane);
     int esh[K];
     uint32_t lmax[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-        const int64_t s = tbase + lane + kWave * m;
-        const bool in = s < S;
-        x0[m] = in ? x[s] : 0.0;
-        x1[m] = in ? x[xs + s] : 0.0;
-        x2[m] = in ? x[2 * xs + s] : 0.0;
-        q[m] = __builtin_fma(x2[m], x2[m], __builtin_fma(x1[m], x1[m], x0[m] * x0[m]));
-        esh[m] = (RESCALE && prev_max) ? ilogb_bits(prev_max[s]) : 0;
+        esh[m] = (RESCALE && prev_max) ? ilogb_bits(prev_max[tbase + lane + kWave * m]) : 0;
         lmax[m] = 0u;
     }
-
-    T *const out_base = cur + tbase + lane;
-    auto store_row = [&](int j, const T *acc) {
-        T *crow = out_base + static_cast<int64_t>(j) * ld;
-#pragma unroll
-        for (int m = 0; m < K; ++m) {
-            T z = acc[m];
-            if constexpr (RESCALE) {
-                z = scale_pow2(z, esh[m]);
-                lmax[m] = max(lmax[m], abs_bits(z));
-            }
-            crow[kWave * m] = z;
-        }
-    };
-
     const int jbeg = min(rg * (4 * ROWS) + wave * ROWS, w_dst);
     const int jend = min(jbeg + ROWS, w_dst);
-    if (jbeg < jend) {
-        int j = jbeg;
-        int e = row_ptr[jbeg];
-        const int e_end = row_ptr[jend];
-        T acc[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m)
-            acc[m] = T(0);
-        // rows without in-edges at the start of this wave's range
-        while (j < jend && row_ptr[j + 1] == e) {
-            store_row(j, acc);
-            ++j;
-        }
-        const EdgeRec *rec = edges + e;
-        // the tile's column block of the previous level; a source row is
-        // reached by a 32-bit byte offset (level buffers are < 2 GiB, which the
-        // planner guarantees by splitting S) and each lane adds its own column
-        const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
-        const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(T));
-        const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(T));
-        while (e < e_end) {
-            const int n = min(kChunk, e_end - e);
-            EdgeRec r[kChunk];
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u)
-                r[u] = rec[u];  // past e_end: the next edges or the zeroed pad, never used
-            // all 4*K source values of the chunk are requested before any is
-            // used; records past the end name rows inside the level buffer
-            // (src < widest level), so the unused reads stay in bounds
-            T v[kChunk][K];
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
-#pragma unroll
-                for (int m = 0; m < K; ++m)
-                    v[u][m] = FROM_ROOT ? T(1) : *reinterpret_cast<const T *>(row + m * kWave * sizeof(T));
-            }
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                if (u < n) {
-#pragma unroll
-                    for (int m = 0; m < K; ++m)
-                        acc[m] = fma_t(edge_factor<T>(r[u], x0[m], x1[m], x2[m], q[m]), v[u][m], acc[m]);
-                    if (r[u].row_end) {
-                        store_row(j, acc);
-                        ++j;
-#pragma unroll
-                        for (int m = 0; m < K; ++m)
-                            acc[m] = T(0);
-                        for (int z = 0; z < r[u].zero_rows && j < jend; ++z) {
-                            store_row(j, acc);
-                            ++j;
-                        }
-                    }
-                }
-            }
-            rec += n;
-            e += n;
-        }
-    }
-
+    level_wave_rows<T, K, FROM_ROOT, RESCALE>(row_ptr, edges, jbeg, jend, prev, cur, ld, tbase, lane, smp, esh,
+                                              lmax);
     if constexpr (RESCALE) {
         if (cur_max) {
-            __shared__ uint32_t red[4][kWave * K];
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                red[wave][lane + kWave * m] = lmax[m];
-            __syncthreads();
-            for (int i = threadIdx.x; i < kWave * K; i += kBlock) {
-                const uint32_t v = max(max(red[0][i], red[1][i]), max(red[2][i], red[3][i]));
-                if (v)
-                    atomicMax(cur_max + tbase + i, v);
-            }
+            __shared__ uint32_t red[4 * kWave * K];
+            fold_max<K, 4>(red, lmax, wave, lane, cur_max + tbase);
         }
     }
 }
@@ -208,45 +104,13 @@ __global__ __launch_bounds__(kBlock) void final_partial_kernel(
     const int tile = blockIdx.x / n_chunks;
     const int c = blockIdx.x - tile * n_chunks;
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
-    double x0[K], x1[K], x2[K], q[K], acc[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) {
-        const int64_t s = tbase + lane + kWave * m;
-        const bool in = s < S;
-        x0[m] = in ? x[s] : 0.0;
-        x1[m] = in ? x[xs + s] : 0.0;
-        x2[m] = in ? x[2 * xs + s] : 0.0;
-        q[m] = __builtin_fma(x2[m], x2[m], __builtin_fma(x1[m], x1[m], x0[m] * x0[m]));
-        acc[m] = 0.0;
-    }
-    constexpr int kQuarter = kFinalChunk / 4;
+    LaneSamples<K> smp;
+    smp.load(x, S, xs, tbase, lane);
     const int c_end = min((c + 1) * kFinalChunk, n_edges);
     const int e_lo = min(c * kFinalChunk + wave * kQuarter, c_end);
     const int e_hi = min(e_lo + kQuarter, c_end);
-    const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
-    const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(TV));
-    const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(TV));
-    for (int e = e_lo; e < e_hi; e += kChunk) {
-        const int n = min(kChunk, e_hi - e);
-        EdgeRec r[kChunk];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            r[u] = edges[e + u];  // the edge array is padded: full chunks are always readable
-        double v[kChunk][K];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                v[u][m] = FROM_ROOT ? 1.0 : static_cast<double>(*reinterpret_cast<const TV *>(row + m * kWave * sizeof(TV)));
-        }
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            if (u < n)
-#pragma unroll
-                for (int m = 0; m < K; ++m)
-                    acc[m] = __builtin_fma(edge_factor64(r[u], x0[m], x1[m], x2[m], q[m]), v[u][m], acc[m]);
-    }
+    double acc[K];
+    final_quarter<TV, K, FROM_ROOT>(edges, e_lo, e_hi, prev, ld, tbase, lane, smp, acc);
     __shared__ double red[4][kWave * K];
 #pragma unroll
     for (int m = 0; m < K; ++m)
@@ -256,28 +120,12 @@ __global__ __launch_bounds__(kBlock) void final_partial_kernel(
         partial[static_cast<int64_t>(c) * ld + tbase + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
-// Final node, pass 2: out[s] = sum over chunks in ascending order, then the
-// binary32 path's accumulated exponent E[s] = sum_{l=1}^{L-2} e_l[s] is applied
-// (or returned separately).
 __global__ __launch_bounds__(kBlock) void final_combine_kernel(
     const double *__restrict__ partial, int32_t n_chunks, int64_t S_pad, int64_t S,
     const uint32_t *__restrict__ maxbits, int32_t L, double *__restrict__ out, int32_t *__restrict__ out_exp) {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (s >= S)
-        return;
-    double v = 0.0;
-    for (int c = 0; c < n_chunks; ++c)
-        v += partial[static_cast<int64_t>(c) * S_pad + s];
-    int E = 0;
-    if (maxbits)
-        for (int l = 1; l <= L - 2; ++l)
-            E += ilogb_bits(maxbits[static_cast<int64_t>(l) * S_pad + s]);
-    if (out_exp) {
-        out[s] = v;
-        out_exp[s] = E;
-    } else {
-        out[s] = ldexp(v, E);
-    }
+    if (s < S)
+        final_combine_one(partial, n_chunks, S_pad, s, maxbits, L, out, out_exp);
 }
 
 __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t *__restrict__ p, uint32_t v, int64_t n) {

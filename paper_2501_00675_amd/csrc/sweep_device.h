@@ -1,0 +1,389 @@
+// Device routines of the level sweep, shared by the standalone kernels
+// (kernels_level.hip, kernels_fused.hip) and the serving step kernel
+// (serve.hip).  Sharing them is what makes a result bit-identical however the
+// work is launched: every node value is one lane's sequential sum over the
+// node's edges in canonical order, with the same factor arithmetic.
+#pragma once
+
+#include "kernels_common.h"
+
+namespace cosdag {
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Edge records fetched per step of a stream (the edge array is padded by as
+// many zeroed records, so a full chunk can always be read).
+constexpr int kChunk = kEdgePad;
+
+// A lane's K samples tbase + lane + 64m: coordinates and |x|^2.  Samples at or
+// beyond S (padding) evaluate with x = 0 and are never returned.
+template <int K>
+struct LaneSamples {
+    double x0[K], x1[K], x2[K], q[K];
+    __device__ __forceinline__ void load(const double *__restrict__ x, int64_t S, int64_t xs, int64_t tbase,
+                                         int lane) {
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            const int64_t s = tbase + lane + kWave * m;
+            const bool in = s < S;
+            x0[m] = in ? x[s] : 0.0;
+            x1[m] = in ? x[xs + s] : 0.0;
+            x2[m] = in ? x[2 * xs + s] : 0.0;
+            q[m] = __builtin_fma(x2[m], x2[m], __builtin_fma(x1[m], x1[m], x0[m] * x0[m]));
+        }
+    }
+};
+
+// One wave computes destination rows [jbeg, jend) of a level for the tile at
+// tbase (64*K samples).  The rows' edges form one contiguous stream, walked in
+// chunks of four: the four records are fetched together (one scalar wait), the
+// 4*K source values requested together (one vector wait), then the factors
+// accumulated.  A row is stored when its flagged last edge has been added;
+// rows without in-edges are stored as zeros.
+//
+// FROM_ROOT: level 1, whose only source is the root (value 1).
+// RESCALE:   binary32 with per-(level, sample) power-of-two scaling: each
+//            stored value is its sum times 2^-esh[m] (exact), and lmax[m]
+//            collects the largest |stored value| bit pattern of the lane.
+// Source rows are reached by 32-bit byte offsets (level buffers < 2 GiB).
+template <typename T, int K, bool FROM_ROOT, bool RESCALE>
+__device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_ptr,
+                                                const EdgeRec *__restrict__ edges, int jbeg, int jend,
+                                                const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
+                                                int64_t tbase, int lane, const LaneSamples<K> &xs,
+                                                const int (&esh)[K], uint32_t (&lmax)[K]) {
+    if (jbeg >= jend)
+        return;
+    T *const out_base = cur + tbase + lane;
+    auto store_row = [&](int j, const T *acc) {
+        T *crow = out_base + static_cast<int64_t>(j) * ld;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            T z = acc[m];
+            if constexpr (RESCALE) {
+                z = scale_pow2(z, esh[m]);
+                lmax[m] = max(lmax[m], abs_bits(z));
+            }
+            crow[kWave * m] = z;
+        }
+    };
+    int j = jbeg;
+    int e = row_ptr[jbeg];
+    const int e_end = row_ptr[jend];
+    T acc[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        acc[m] = T(0);
+    // rows without in-edges at the start of the range
+    while (j < jend && row_ptr[j + 1] == e) {
+        store_row(j, acc);
+        ++j;
+    }
+    const EdgeRec *rec = edges + e;
+    const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
+    const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(T));
+    const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(T));
+    while (e < e_end) {
+        const int n = min(kChunk, e_end - e);
+        EdgeRec r[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            r[u] = rec[u];  // past e_end: later edges or the zeroed pad, never used
+        // all 4*K source values are requested before any is used; records past
+        // the end name rows inside the level buffer (src < widest level), so
+        // the unused reads stay in bounds
+        T v[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                v[u][m] = FROM_ROOT ? T(1) : *reinterpret_cast<const T *>(row + m * kWave * sizeof(T));
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            if (u < n) {
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    acc[m] = fma_t(edge_factor<T>(r[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]), v[u][m], acc[m]);
+                if (r[u].row_end) {
+                    store_row(j, acc);
+                    ++j;
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        acc[m] = T(0);
+                    for (int z = 0; z < r[u].zero_rows && j < jend; ++z) {
+                        store_row(j, acc);
+                        ++j;
+                    }
+                }
+            }
+        }
+        rec += n;
+        e += n;
+    }
+}
+
+// Largest |value| bit patterns of NW waves (lmax of each lane) combined in LDS
+// and folded into cur_max[0 .. 64K) by integer atomic max (order-free).  All
+// threads of the group must call it (it synchronises the group).
+template <int K, int NW>
+__device__ __forceinline__ void fold_max(uint32_t *red /* LDS [NW][64K] */, const uint32_t (&lmax)[K], int wave,
+                                         int lane, uint32_t *__restrict__ cur_max) {
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        red[wave * (kWave * K) + lane + kWave * m] = lmax[m];
+    __syncthreads();
+    for (int i = threadIdx.x; i < kWave * K; i += NW * kWave) {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            v = max(v, red[w * (kWave * K) + i]);
+        if (v)
+            atomicMax(cur_max + i, v);
+    }
+    __syncthreads();
+}
+
+// Sum over final-node edges [e_lo, e_hi) of w_e(x) v_{L-1}[src_e] in binary64,
+// sequentially in canonical order (one quarter of a final-node chunk).
+template <typename TV, int K, bool FROM_ROOT>
+__device__ __forceinline__ void final_quarter(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
+                                              const TV *__restrict__ prev, int64_t ld, int64_t tbase, int lane,
+                                              const LaneSamples<K> &xs, double (&acc)[K]) {
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        acc[m] = 0.0;
+    const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
+    const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(TV));
+    const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(TV));
+    for (int e = e_lo; e < e_hi; e += kChunk) {
+        const int n = min(kChunk, e_hi - e);
+        EdgeRec r[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            r[u] = edges[e + u];
+        double v[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                v[u][m] = FROM_ROOT ? 1.0 : static_cast<double>(*reinterpret_cast<const TV *>(row + m * kWave * sizeof(TV)));
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            if (u < n)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    acc[m] = __builtin_fma(edge_factor64(r[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]), v[u][m], acc[m]);
+    }
+}
+
+// Final node, second pass for sample s: the chunk partial sums added in
+// ascending chunk order, then the binary32 path's accumulated exponent
+// E[s] = sum_{l=1}^{L-2} e_l[s] applied (or returned separately).
+__device__ __forceinline__ void final_combine_one(const double *__restrict__ partial, int32_t n_chunks, int64_t S_pad,
+                                                  int64_t s, const uint32_t *__restrict__ maxbits, int32_t L,
+                                                  double *__restrict__ out, int32_t *__restrict__ out_exp) {
+    double v = 0.0;
+    for (int c = 0; c < n_chunks; ++c)
+        v += partial[static_cast<int64_t>(c) * S_pad + s];
+    int E = 0;
+    if (maxbits)
+        for (int l = 1; l <= L - 2; ++l)
+            E += ilogb_bits(maxbits[static_cast<int64_t>(l) * S_pad + s]);
+    if (out_exp) {
+        out[s] = v;
+        out_exp[s] = E;
+    } else {
+        out[s] = ldexp(v, E);
+    }
+}
+
+// final_quarter with the level L-1 values read from LDS ([node][64K]).
+template <typename T, int K>
+__device__ __forceinline__ void final_quarter_lds(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
+                                                  const T *vals, int lane, const LaneSamples<K> &xs,
+                                                  double (&acc)[K]) {
+    constexpr int kTile = kWave * K;
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        acc[m] = 0.0;
+    for (int e = e_lo; e < e_hi; e += kChunk) {
+        const int n = min(kChunk, e_hi - e);
+        EdgeRec r[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            r[u] = edges[e + u];
+        double v[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                v[u][m] = static_cast<double>(vals[r[u].src * kTile + lane + kWave * m]);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            if (u < n)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    acc[m] = __builtin_fma(edge_factor64(r[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]), v[u][m], acc[m]);
+    }
+}
+
+// ---------------------------------------------------------------- fused sweep
+
+constexpr int kFusedWaves = 16;
+constexpr int kFusedThreads = kFusedWaves * kWave;
+constexpr int kQuarter = kFinalChunk / 4;
+
+// Everything a workgroup needs to sweep one graph for one tile in LDS.
+struct FusedGraph {
+    const int32_t *row_ptr;
+    const EdgeRec *edges;
+    const LevelDev *levels;
+    int32_t L;
+    const double *x;
+    int64_t S;
+    double *out;
+    int32_t *out_exp;
+};
+
+// Whole-graph sweep for the tile at tbase (64*K samples) by a group of 16
+// waves, the level held in LDS as [node][64K] (vals), wave w owning rows
+// [w*RMAX, (w+1)*RMAX).  red: [16][64K] uint32 (RESCALE only); part:
+// [quarters][64K] binary64.  The final node is reduced in quarters of 64 edges
+// combined exactly as final_partial / final_combine do.
+template <typename T, int K, int RMAX, bool RESCALE>
+__device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T *vals, uint32_t *red, double *part,
+                                           int wave, int lane) {
+    constexpr int kTile = kWave * K;
+    LaneSamples<K> xs;
+    xs.load(G.x, G.S, G.S, tbase, lane);
+    int esh[K], E[K];  // e_{l-1} and the sum of e_1 .. e_{L-2} for this lane's samples
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        esh[m] = 0;
+        E[m] = 0;
+    }
+    for (int l = 1; l < G.L; ++l) {
+        const LevelDev lv = G.levels[l - 1];
+        const int32_t *rp = G.row_ptr + lv.rp_begin;
+        const int jb = min(wave * RMAX, lv.w_dst);
+        const int nb = min(jb + RMAX, lv.w_dst) - jb;
+        // lane i (i <= nb) holds the start of row jb + i: one load per wave and level
+        const int rpl = lane <= nb ? rp[jb + lane] : 0;
+        T acc[RMAX][K];
+        uint32_t lmax[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            lmax[m] = 0u;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                acc[r][m] = T(0);
+            if (r < nb) {
+                const int e1 = __builtin_amdgcn_readlane(rpl, r + 1);
+                for (int e = __builtin_amdgcn_readlane(rpl, r); e < e1; e += kChunk) {
+                    const int n = min(kChunk, e1 - e);
+                    EdgeRec rr[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u)
+                        rr[u] = G.edges[e + u];
+                    // records past the row name rows < widest level: the
+                    // unused LDS reads stay in bounds
+                    T v[kChunk][K];
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+                        for (int m = 0; m < K; ++m)
+                            v[u][m] = (l == 1) ? T(1) : vals[rr[u].src * kTile + lane + kWave * m];
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u)
+                        if (u < n)
+#pragma unroll
+                            for (int m = 0; m < K; ++m)
+                                acc[r][m] = fma_t(edge_factor<T>(rr[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]),
+                                                  v[u][m], acc[r][m]);
+                }
+                if constexpr (RESCALE) {
+#pragma unroll
+                    for (int m = 0; m < K; ++m) {
+                        acc[r][m] = scale_pow2(acc[r][m], esh[m]);
+                        lmax[m] = max(lmax[m], abs_bits(acc[r][m]));
+                    }
+                }
+            }
+        }
+        __syncthreads();  // every wave has finished reading level l-1
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+            if (r < nb)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    vals[(jb + r) * kTile + lane + kWave * m] = acc[r][m];
+        if constexpr (RESCALE)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                red[wave * kTile + lane + kWave * m] = lmax[m];
+        __syncthreads();  // level l complete
+        if constexpr (RESCALE) {
+            if (l <= G.L - 2) {
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    uint32_t mx = 0u;
+#pragma unroll
+                    for (int w = 0; w < kFusedWaves; ++w)
+                        mx = max(mx, red[w * kTile + lane + kWave * m]);
+                    esh[m] = ilogb_bits(mx);
+                    E[m] += esh[m];
+                }
+            }
+        }
+    }
+
+    // final node: quarter p holds edges [64p, 64p + 64) of the last level
+    const LevelDev lf = G.levels[G.L - 1];
+    const int nq = (lf.n_edges + kQuarter - 1) / kQuarter;
+    for (int p = wave; p < nq; p += kFusedWaves) {
+        double acc[K];
+        const int e_lo = p * kQuarter;
+        const int e_hi = min(e_lo + kQuarter, lf.n_edges);
+        if (G.L == 1)
+            final_quarter<T, K, true>(G.edges + lf.e_begin, e_lo, e_hi, nullptr, 0, 0, lane, xs, acc);
+        else
+            final_quarter_lds<T, K>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xs, acc);
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            part[p * kTile + lane + kWave * m] = acc[m];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            const int64_t s = tbase + lane + kWave * m;
+            if (s >= G.S)
+                continue;
+            double tot = 0.0;
+            const int nc = (nq + 3) / 4;
+            for (int c = 0; c < nc; ++c) {
+                double cs = part[(4 * c) * kTile + lane + kWave * m];
+#pragma unroll
+                for (int i = 1; i < 4; ++i)
+                    cs += (4 * c + i < nq) ? part[(4 * c + i) * kTile + lane + kWave * m] : 0.0;
+                tot += cs;
+            }
+            if (G.out_exp) {
+                G.out[s] = tot;
+                G.out_exp[s] = E[m];
+            } else {
+                G.out[s] = ldexp(tot, E[m]);
+            }
+        }
+    }
+    __syncthreads();  // part and vals may be reused by the group's next tile
+}
+
+}  // namespace cosdag
