@@ -1,13 +1,16 @@
 """Benchmark: edge-sample updates/s of the leveled-DAG level sweep on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload mid] [--precision fp64]
+    python bench.py [--steps K] [--warmup W] [--workload mid] [--precision fp64] [--no-serving]
 
 One step = one full evaluation (every level, the final-node reduction, and for
 the rescaled FP32 path the exponent bookkeeping) of the workload's graph for
 all S samples, with the graph, the samples and the workspace already resident
 in HBM.  Prints one JSON line.  The CPU-baseline leg times the plain FP64
 oracle on the host cores; its outputs are also the reference for the reported
-error of the GPU results.
+error of the GPU results.  The serving leg ("serving" in the JSON) replays the
+serving request stream through the continuous-batching server and through
+one-at-a-time evaluation, and reports p50/p99 request latency beside
+throughput.
 """
 
 from __future__ import annotations
@@ -216,6 +219,134 @@ def calibrate_copy(steps: int, nbytes: int = 1 << 30):
                       "copy_GBps": 2 * nbytes / (ms / 1000) / 1e9}), flush=True)
 
 
+SERVING_TEXT = ("serving: 512 resident graphs, L~U{4..20}, interior width log-U[16,2048], in-degree U{2..8}; "
+                "4096 requests, S~log-U[256,8192], x~U[-1,1]^3; t=0 burst and Poisson arrivals")
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v, np.float64), q))
+
+
+def serving_leg(P, args):
+    """Continuous-batching server vs one-at-a-time cos_evaluate on the serving request stream.
+
+    Runs: a t=0 burst of every request (batched FP64, batched FP32-rescaled), then Poisson arrivals at
+    load x the measured batched-FP64 capacity, each trace replayed by batched FP64, batched FP32-rescaled
+    and single-request FP64 (cos_evaluate, one request at a time, in arrival order).  Latency of a request =
+    completion - arrival; throughput = total edge-samples / (last completion - first arrival).
+    """
+    import torch
+
+    from workloads import serving_mix
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    graphs, reqs = serving_mix()
+    print(f"# serving: {len(graphs)} graphs, {len(reqs)} requests generated in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    Gs = [P.Graph.from_leveled(g) for g in graphs]
+    es = np.array([graphs[r["graph"]].n_edges * r["S"] for r in reqs], np.float64)
+    total_es = float(es.sum())
+    Ss = np.array([r["S"] for r in reqs])
+    off = np.concatenate([[0], np.cumsum(Ss)])
+    xs = [torch.from_numpy(r["x"]).to(dev) for r in reqs]
+    outs = {k: torch.empty(int(off[-1]), dtype=torch.float64, device=dev) for k in ("fp64", "fp32r", "single")}
+
+    def out_view(kind, i):
+        return outs[kind][int(off[i]):int(off[i + 1])]
+
+    ws = torch.empty(max(G.workspace_bytes(int(S), "fp64") for G, S in ((Gs[r["graph"]], r["S"]) for r in reqs)),
+                     dtype=torch.uint8, device=dev)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = P.Server(budget, args.serve_slots)
+    gids = [srv.add_graph(G) for G in Gs]
+    torch.cuda.synchronize()
+
+    def batched(precision, arrivals_ns, n=None):
+        n = len(reqs) if n is None else n
+        before = srv.stats()
+        t0 = time.monotonic_ns() + 1_000_000
+        tickets = []
+        for i in range(n):
+            target = t0 + int(arrivals_ns[i])
+            while time.monotonic_ns() < target:
+                pass
+            tickets.append(srv.submit(gids[reqs[i]["graph"]], xs[i], precision, out=out_view(precision, i),
+                                      sync_inputs=False))
+        st = [srv.wait(t) for t in tickets]
+        after = srv.stats()
+        done = np.array([d["t_done_ns"] for d in st], np.float64)
+        lat = (done - (t0 + np.asarray(arrivals_ns[:n], np.float64))) / 1e6
+        span = (done.max() - t0) / 1e9
+        return {"value": float(es[:n].sum()) / span, "makespan_ms": span * 1e3, "p50_ms": _pct(lat, 50),
+                "p99_ms": _pct(lat, 99), "steps": after["steps"] - before["steps"],
+                "max_step_requests": after["max_step_requests"], "max_active": after["max_active"],
+                "peak_workspace_bytes": after["peak_bytes"]}
+
+    def single(arrivals_ns, n=None):
+        n = len(reqs) if n is None else n
+        stream = torch.cuda.current_stream(dev)
+        t0 = time.monotonic_ns() + 1_000_000
+        done = np.empty(n)
+        for i in range(n):
+            target = t0 + int(arrivals_ns[i])
+            while time.monotonic_ns() < target:
+                pass
+            Gs[reqs[i]["graph"]].evaluate(xs[i], "fp64", out=out_view("single", i), workspace=ws)
+            stream.synchronize()
+            done[i] = time.monotonic_ns()
+        lat = (done - (t0 + np.asarray(arrivals_ns[:n], np.float64))) / 1e6
+        span = (done.max() - t0) / 1e9
+        return {"value": float(es[:n].sum()) / span, "makespan_ms": span * 1e3, "p50_ms": _pct(lat, 50),
+                "p99_ms": _pct(lat, 99)}
+
+    zeros = np.zeros(len(reqs))
+    for p in ("fp64", "fp32r"):  # warm-up: code objects, first-touch of the arena
+        batched(p, zeros, n=256)
+    single(zeros, n=64)
+    res = {"workload": SERVING_TEXT, "requests": len(reqs), "graphs": len(graphs), "total_edge_samples": total_es,
+           "server": {"hbm_budget_bytes": budget, "max_slots": args.serve_slots}}
+    res["burst"] = {p: batched(p, zeros) for p in ("fp64", "fp32r")}
+    res["burst"]["fp64_single"] = single(zeros)
+    cap_rps = len(reqs) / (res["burst"]["fp64"]["makespan_ms"] / 1e3)
+    rng = np.random.default_rng(4)
+    gaps = rng.exponential(1.0, len(reqs))
+    res["poisson"] = {}
+    for load in args.serve_loads:
+        rate = load * cap_rps
+        arr = np.cumsum(gaps) / rate * 1e9
+        arr -= arr[0]
+        print(f"# serving poisson load {load}: {rate:.0f} requests/s", file=sys.stderr, flush=True)
+        res["poisson"][str(load)] = {"rate_rps": rate, "fp64_batched": batched("fp64", arr),
+                                     "fp32r_batched": batched("fp32r", arr), "fp64_single": single(arr)}
+    torch.cuda.synchronize()
+    # results of the last trace: batched FP64 bit-identical to one-at-a-time FP64 for every request
+    same = torch.eq(outs["fp64"].view(torch.int64), outs["single"].view(torch.int64))
+    res["fp64_batched_bit_identical_to_single"] = bool(same.all().item())
+    # oracle check of a seeded subset of requests (64 requests, up to 128 samples each)
+    if not args.no_cpu_baseline:
+        import oracle
+
+        pick = np.random.default_rng(5).choice(len(reqs), 64, replace=False)
+        worst = {"fp64": 0.0, "fp32r": 0.0}
+        ok = True
+        for i in pick:
+            r = reqs[i]
+            idx = np.unique(np.random.default_rng(int(i)).choice(r["S"], min(r["S"], 128), replace=False))
+            xr = np.ascontiguousarray(r["x"][:, idx])
+            V = oracle.sweep(graphs[r["graph"]], xr, "value")
+            Q = oracle.sweep(graphs[r["graph"]], xr, "square")
+            for p in worst:
+                y = out_view(p, i).cpu().numpy()[idx]
+                e = float(oracle.scaled_error(y, V, Q).max())
+                worst[p] = max(worst[p], e)
+                ok &= e <= TOL[p]
+        res["accuracy"] = {"requests_checked": 64, "samples_per_request": "<=128", "scaled_max": worst,
+                           "pass": bool(ok)}
+    srv.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +359,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain 1 GiB device copy (reference for HBM counters and bandwidth)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-budget-gib", type=float, default=24.0)
+    ap.add_argument("--serve-loads", type=lambda v: [float(t) for t in v.split(",") if t], default=[0.5, 0.9])
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy(args.steps)
@@ -243,6 +379,9 @@ def main():
     import paper_2501_00675_amd as P
     from workloads import make_config
 
+    if args.serving_only:
+        print(json.dumps({"serving": serving_leg(P, args)}), flush=True)
+        return
     g, x = make_config(args.workload)
     S = x.shape[1]
     E = g.n_edges
@@ -284,6 +423,8 @@ def main():
     for d in variants.values():
         d.pop("_y", None)
     result["variants"] = variants
+    if not args.no_serving:
+        result["serving"] = serving_leg(P, args)
     print(json.dumps(result), flush=True)
 
 

@@ -186,6 +186,88 @@ cos_status cos_evaluate(const cos_graph *g, const double *x_dev, int64_t S, cos_
    reads it.  NULL is a no-op.  Errors: COS_EDEVICE if hipFree fails. */
 cos_status cos_destroy_graph(cos_graph *g);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A server evaluates requests (graph, samples, precision) submitted at any
+ * time against graphs that stay resident on the device -- the paper's picture
+ * of thousands of configurations in flight (Sec. II.C, Sec. III) applied to a
+ * stream of requests.  Requests are admitted while a slot is free and their
+ * device workspace fits in an HBM budget; every admitted request advances by
+ * one stage per step, where a step is one level-synchronous launch shared by
+ * all admitted requests (replayed from an instantiated HIP graph): a graph whose
+ * widest level fits in LDS completes in one step, a wider graph advances one
+ * level per step, then its final node in two more.  Requests that arrive while
+ * others run join the next step (continuous batching).  Each result is
+ * bit-identical to cos_evaluate on the same graph, samples and precision.
+ */
+typedef struct cos_server cos_server;
+
+typedef struct cos_req_stats {
+    int64_t t_submit_ns;  /* steady-clock time stamps (ns); 0 when not reached */
+    int64_t t_admit_ns;
+    int64_t t_done_ns;
+    int32_t status;       /* COS_OK done, COS_EAGAIN queued or running, COS_ECANCELED, or a failure */
+    int32_t steps;        /* steps the request took part in */
+    int64_t first_step;   /* index of its first step, -1 before admission */
+    int64_t footprint;    /* device workspace bytes it holds while admitted */
+} cos_req_stats;
+
+typedef struct cos_server_stats {
+    int64_t submitted, completed, cancelled, failed;
+    int64_t steps;              /* step launches */
+    int64_t items;              /* work items over all steps */
+    int64_t max_active;         /* most requests admitted at once */
+    int64_t max_step_requests;  /* most requests sharing one step */
+    uint64_t budget_bytes;      /* HBM budget for request workspaces */
+    uint64_t peak_bytes;        /* largest sum of admitted workspaces */
+} cos_server_stats;
+
+/*
+ * Create a server on the current device.  hbm_budget: bytes of device memory
+ * the server allocates once and hands out as request workspaces (a graph whose
+ * widest level fits in LDS needs none); max_slots: requests admitted at once,
+ * 1..512.  Starts a scheduling thread.  Errors: COS_EINVAL, COS_ENOMEM,
+ * COS_EDEVICE.
+ */
+cos_status cos_server_create(uint64_t hbm_budget, int32_t max_slots, cos_server **out);
+
+/* Register a graph (it must outlive the server) and get its id.
+   Errors: COS_EINVAL (NULL, graph on another device). */
+cos_status cos_server_add_graph(cos_server *srv, const cos_graph *g, int32_t *gid);
+
+/*
+ * Queue a request: x_dev device float64[3][S], out_dev device float64[S],
+ * out_exp_dev device int32[S] or NULL (as for cos_evaluate).  The caller keeps
+ * them alive until the request ends (poll/wait return a final status).  Never
+ * blocks.  Errors: COS_EINVAL (unknown gid, S < 1, bad precision, S too large
+ * for one sweep), COS_ENOMEM (the request's workspace exceeds the whole
+ * budget, so it could never be admitted).
+ */
+cos_status cos_server_submit(cos_server *srv, int32_t gid, const double *x_dev, int64_t S, cos_precision p,
+                             double *out_dev, int32_t *out_exp_dev, uint64_t *ticket);
+
+/*
+ * Status of a request.  Returns COS_EAGAIN while queued or running; once the
+ * request has ended it returns its final status (COS_OK, COS_ECANCELED or the
+ * failure), fills *stats (nullable) and forgets the ticket.
+ * Errors: COS_EINVAL (unknown ticket).
+ */
+cos_status cos_server_poll(cos_server *srv, uint64_t ticket, cos_req_stats *stats);
+
+/* As cos_server_poll, but blocks until the request has ended. */
+cos_status cos_server_wait(cos_server *srv, uint64_t ticket, cos_req_stats *stats);
+
+/* Cancel a request that has not been admitted yet.  Returns COS_OK, or
+   COS_EAGAIN if it is already running (it will complete).  Errors: COS_EINVAL. */
+cos_status cos_server_cancel(cos_server *srv, uint64_t ticket);
+
+/* Counters of the server's lifetime.  Errors: COS_EINVAL on NULL. */
+cos_status cos_server_get_stats(cos_server *srv, cos_server_stats *stats);
+
+/* Cancel queued requests, wait for admitted ones, stop the scheduling thread
+   and free the server's device memory.  NULL is a no-op. */
+cos_status cos_server_destroy(cos_server *srv);
+
 /*
  * Kernel timing probe (for benchmarks).  While enabled, every kernel the
  * library queues is bracketed by a pair of HIP events recorded on the same

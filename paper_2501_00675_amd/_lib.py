@@ -29,6 +29,8 @@ EXPORTS = [
     "cos_last_error", "cos_build_id", "cos_abi_version", "cos_create_graph", "cos_graph_get_info",
     "cos_graph_export", "cos_evaluate_workspace_size", "cos_evaluate", "cos_destroy_graph",
     "cos_timing_enable", "cos_timing_read", "cos_graph_set_path",
+    "cos_server_create", "cos_server_add_graph", "cos_server_submit", "cos_server_poll", "cos_server_wait",
+    "cos_server_cancel", "cos_server_get_stats", "cos_server_destroy",
 ]
 PATHS = {"auto": 0, "streamed": 1, "fused": 2}
 
@@ -43,6 +45,19 @@ class GraphInfo(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("fused_mask", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_edges", ctypes.c_int64), ("max_width", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
                 ("final_in_degree", ctypes.c_int64), ("device_bytes", ctypes.c_uint64)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("steps", ctypes.c_int32), ("first_step", ctypes.c_int64),
+                ("footprint", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("steps", ctypes.c_int64), ("items", ctypes.c_int64),
+                ("max_active", ctypes.c_int64), ("max_step_requests", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64)]
 
 
 def _hip_runtimes_mapped() -> set:
@@ -80,6 +95,21 @@ def _bind(lib):
     lib.cos_timing_enable.argtypes = [i32]
     lib.cos_timing_read.restype = i32
     lib.cos_timing_read.argtypes = [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.cos_server_create.restype = i32
+    lib.cos_server_create.argtypes = [u64, i32, ctypes.POINTER(p)]
+    lib.cos_server_add_graph.restype = i32
+    lib.cos_server_add_graph.argtypes = [p, p, ctypes.POINTER(i32)]
+    lib.cos_server_submit.restype = i32
+    lib.cos_server_submit.argtypes = [p, i32, p, i64, i32, p, p, ctypes.POINTER(u64)]
+    for name in ("cos_server_poll", "cos_server_wait"):
+        getattr(lib, name).restype = i32
+        getattr(lib, name).argtypes = [p, u64, ctypes.POINTER(ReqStats)]
+    lib.cos_server_cancel.restype = i32
+    lib.cos_server_cancel.argtypes = [p, u64]
+    lib.cos_server_get_stats.restype = i32
+    lib.cos_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
+    lib.cos_server_destroy.restype = i32
+    lib.cos_server_destroy.argtypes = [p]
     return lib
 
 

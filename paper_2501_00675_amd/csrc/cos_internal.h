@@ -100,6 +100,8 @@ constexpr int kBlock = 256;          // 4 wavefronts per workgroup (streamed ker
 constexpr int kSamplePad = 256;      // S is padded to a multiple of this
 constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
 constexpr int kFinalChunk = 256;     // final-node edges per partial sum (4 quarters of 64)
+constexpr int kQuarter = kFinalChunk / 4;
+constexpr int kFusedWaves = 16;      // wavefronts per workgroup of the LDS-resident sweep
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -120,6 +122,8 @@ constexpr int64_t kMaxLevelBytes = int64_t(1) << 31;
 Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p);
 // Natural plan for S samples: fused if it fits, else the largest chunk allowed.
 Workspace plan_workspace(const Graph &g, int64_t S, cos_precision p);
+// Largest sample chunk whose level buffer stays below kMaxLevelBytes.
+int64_t max_chunk(const Graph &g, cos_precision p);
 
 // Kernel launchers.  All return hipSuccess or the launch error.  x points at
 // the chunk's first sample; xs is the distance between coordinate rows of x.

@@ -2,7 +2,7 @@
 // rows-per-wave variant and the samples-per-lane K a graph can use.
 #pragma once
 
-#include "sweep_device.h"
+#include "cos_internal.h"
 
 namespace cosdag {
 

@@ -1,6 +1,7 @@
 // Host side of the library: errors, graph ingest (validation, canonical order,
 // per-level CSR, parameter records), upload, introspection and the timing probe.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -40,7 +41,7 @@ struct TimingRec {
     hipEvent_t start, stop;
 };
 std::mutex g_tmu;
-bool g_timing = false;
+std::atomic<bool> g_timing{false};  // read without the lock by launching threads
 std::vector<TimingRec> g_recs;
 std::vector<hipEvent_t> g_pool;
 thread_local hipEvent_t t_open_start[KK_COUNT] = {};

@@ -12,6 +12,7 @@
 #include <atomic>
 
 #include "fused_plan.h"
+#include "sweep_device.h"
 
 namespace cosdag {
 namespace {

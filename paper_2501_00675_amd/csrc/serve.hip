@@ -1,0 +1,258 @@
+// Serving step kernels: one level-synchronous step advances every admitted
+// request by one stage (paper Sec. II.C: levels in sequence; a step keeps each
+// request's levels in order while different requests share the launch, the
+// many configurations in flight of Sec. II.C and Sec. III).
+//
+// A step is a graph of three nodes: the upload of the step table, then two
+// independent kernels that read it.  serve_fused_kernel (16 waves, levels in
+// LDS) sweeps whole narrow graphs, 64 samples per item; serve_stream_kernel
+// (4 waves, the shape of the standalone streamed kernels) runs one interior
+// level, the final-node partial sums or the final combine of the wide graphs.
+// Work items are numbered per section and taken grid-stride.  Every item runs
+// the same device routines as the standalone kernels, so a request's result is
+// bit-identical to cos_evaluate alone, whatever it shares a step with.
+#include <atomic>
+
+#include "fused_plan.h"
+#include "serve_types.h"
+#include "sweep_device.h"
+
+namespace cosdag {
+namespace {
+
+constexpr int kServeFusedGrid = 256;    // one 16-wave group per CU
+constexpr int kServeStreamGrid = 2048;  // eight 4-wave groups per CU
+
+// Entry of [lo, lo + n) whose items contain `item` (item_base ascending).
+__device__ __forceinline__ uint32_t find_entry(const StepTable *__restrict__ t, uint32_t lo, uint32_t n,
+                                               uint32_t item) {
+    uint32_t hi = lo + n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (t->e[mid].item_base <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, int RMAX, bool RESCALE>
+__device__ __forceinline__ void serve_fused(const ServeReqDev &r, uint32_t tile, unsigned char *lds, int wave,
+                                            int lane) {
+    if constexpr (acc_fits(sizeof(T), 1, RMAX)) {
+        const FusedGraph G{r.row_ptr, r.edges, r.levels, r.L, r.x, r.S, r.out, r.out_exp};
+        fused_tile<T, 1, RMAX, RESCALE>(G, static_cast<int64_t>(tile) * kWave, reinterpret_cast<T *>(lds),
+                                        reinterpret_cast<uint32_t *>(lds + r.off_red),
+                                        reinterpret_cast<double *>(lds + r.off_part), wave, lane);
+    }
+}
+
+template <typename T, bool RESCALE>
+__device__ __forceinline__ void serve_fused_rows(const ServeReqDev &r, uint32_t tile, unsigned char *lds, int wave,
+                                                 int lane) {
+    switch (r.rows_variant) {
+    case 2:
+        serve_fused<T, 2, RESCALE>(r, tile, lds, wave, lane);
+        break;
+    case 4:
+        serve_fused<T, 4, RESCALE>(r, tile, lds, wave, lane);
+        break;
+    case 8:
+        serve_fused<T, 8, RESCALE>(r, tile, lds, wave, lane);
+        break;
+    case 16:
+        serve_fused<T, 16, RESCALE>(r, tile, lds, wave, lane);
+        break;
+    case 24:
+        serve_fused<T, 24, RESCALE>(r, tile, lds, wave, lane);
+        break;
+    default:
+        serve_fused<T, kMaxRows, RESCALE>(r, tile, lds, wave, lane);
+        break;
+    }
+}
+
+// Interior level l for a row group of 32 rows (8 per wave) and a tile of 256
+// samples; the level buffers alternate as in the standalone sweep.
+template <typename T, bool RESCALE>
+__device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_t local, uint32_t n_rg,
+                                            uint32_t *red, int wave, int lane) {
+    constexpr int K = kServeLevelK;
+    const uint32_t rg = local % n_rg;
+    const uint32_t tile = local / n_rg;
+    const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
+    const LevelDev lv = r.levels[l - 1];
+    T *const b0 = reinterpret_cast<T *>(r.ws + r.off_buf0);
+    T *const b1 = reinterpret_cast<T *>(r.ws + r.off_buf1);
+    T *cur = (l - 1) & 1 ? b1 : b0;
+    const T *prev = (l - 2) & 1 ? b1 : b0;
+    uint32_t *maxbits = reinterpret_cast<uint32_t *>(r.ws + r.off_maxbits);
+    LaneSamples<K> smp;
+    smp.load(r.x, r.S, r.S, tbase, lane);
+    int esh[K];
+    uint32_t lmax[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        esh[m] = (RESCALE && l >= 2) ? ilogb_bits(maxbits[static_cast<int64_t>(l - 1) * r.S_pad + tbase + lane + kWave * m])
+                                     : 0;
+        lmax[m] = 0u;
+    }
+    const int jbeg = min(static_cast<int>(rg) * kServeLevelRowsPerItem + wave * kServeLevelRows, lv.w_dst);
+    const int jend = min(jbeg + kServeLevelRows, lv.w_dst);
+    const int32_t *rp = r.row_ptr + lv.rp_begin;
+    if (l == 1)
+        level_wave_rows<T, K, true, RESCALE>(rp, r.edges, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
+                                             lmax);
+    else
+        level_wave_rows<T, K, false, RESCALE>(rp, r.edges, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
+                                              lmax);
+    if constexpr (RESCALE) {
+        if (l <= r.L - 2)
+            fold_max<K, 4>(red, lmax, wave, lane, maxbits + static_cast<int64_t>(l) * r.S_pad + tbase);
+    }
+}
+
+// Final-node partial sums of one chunk of 256 edges (wave w: quarter w) for a
+// tile of 128 samples, combined as ((q0 + q1) + q2) + q3 exactly as
+// final_partial_kernel does.
+template <typename TV>
+__device__ __forceinline__ void serve_final(const ServeReqDev &r, uint32_t local, double *red, int wave, int lane) {
+    constexpr int K = kServeFinalK;
+    const uint32_t n_chunks = static_cast<uint32_t>(r.final_chunks);
+    const int c = static_cast<int>(local % n_chunks);
+    const int64_t tbase = static_cast<int64_t>(local / n_chunks) * (kWave * K);
+    const LevelDev lf = r.levels[r.L - 1];
+    LaneSamples<K> smp;
+    smp.load(r.x, r.S, r.S, tbase, lane);
+    const int c_end = min((c + 1) * kFinalChunk, lf.n_edges);
+    const int e_lo = min(c * kFinalChunk + wave * kQuarter, c_end);
+    const int e_hi = min(e_lo + kQuarter, c_end);
+    double acc[K];
+    const EdgeRec *edges = r.edges + lf.e_begin;
+    if (r.L == 1) {
+        final_quarter<double, K, true>(edges, e_lo, e_hi, nullptr, r.S_pad, tbase, lane, smp, acc);
+    } else {
+        const TV *prev = reinterpret_cast<const TV *>(r.ws + ((r.L - 2) & 1 ? r.off_buf1 : r.off_buf0));
+        final_quarter<TV, K, false>(edges, e_lo, e_hi, prev, r.S_pad, tbase, lane, smp, acc);
+    }
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        red[wave * (kWave * K) + lane + kWave * m] = acc[m];
+    __syncthreads();
+    double *partial = reinterpret_cast<double *>(r.ws + r.off_partial);
+    for (int i = threadIdx.x; i < kWave * K; i += kBlock)
+        partial[static_cast<int64_t>(c) * r.S_pad + tbase + i] =
+            ((red[i] + red[kWave * K + i]) + red[2 * kWave * K + i]) + red[3 * kWave * K + i];
+}
+
+__global__ __launch_bounds__(kFusedThreads) void serve_fused_kernel(const StepTable *__restrict__ tab,
+                                                                    const ServeReqDev *__restrict__ reqs) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t n = tab->n_fused;
+    const uint32_t total = tab->items_fused;
+    for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const StepEntry &en = tab->e[find_entry(tab, 0, n, item)];
+        const ServeReqDev &r = reqs[en.slot];
+        const uint32_t tile = item - en.item_base;
+        if (r.precision == COS_FP64)
+            serve_fused_rows<double, false>(r, tile, lds, wave, lane);
+        else if (r.precision == COS_FP32_RESCALED)
+            serve_fused_rows<float, true>(r, tile, lds, wave, lane);
+        else
+            serve_fused_rows<float, false>(r, tile, lds, wave, lane);
+        // fused_tile ends with a group barrier, so LDS is free for the next item
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *__restrict__ tab,
+                                                              const ServeReqDev *__restrict__ reqs) {
+    __shared__ __align__(16) unsigned char lds[4 * kWave * kServeLevelK * sizeof(uint32_t)];
+    static_assert(sizeof(lds) >= 4 * kWave * kServeFinalK * sizeof(double), "final-node staging");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lo = tab->n_fused;
+    const uint32_t n = tab->n_streamed;
+    const uint32_t total = tab->items_streamed;
+    for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const StepEntry &en = tab->e[find_entry(tab, lo, n, item)];
+        const ServeReqDev &r = reqs[en.slot];
+        const uint32_t local = item - en.item_base;
+        const uint32_t kind = en.kind;
+        if (kind == SK_LEVEL) {
+            const int l = static_cast<int>(en.level);
+            uint32_t *red = reinterpret_cast<uint32_t *>(lds);
+            if (r.precision == COS_FP64)
+                serve_level<double, false>(r, l, local, en.n_rg, red, wave, lane);
+            else if (r.precision == COS_FP32_RESCALED)
+                serve_level<float, true>(r, l, local, en.n_rg, red, wave, lane);
+            else
+                serve_level<float, false>(r, l, local, en.n_rg, red, wave, lane);
+        } else if (kind == SK_FINAL) {
+            double *red = reinterpret_cast<double *>(lds);
+            if (r.precision == COS_FP64)
+                serve_final<double>(r, local, red, wave, lane);
+            else
+                serve_final<float>(r, local, red, wave, lane);
+        } else {  // SK_COMBINE
+            const int64_t s = static_cast<int64_t>(local) * kServeCombineTile + threadIdx.x;
+            if (s < r.S)
+                final_combine_one(reinterpret_cast<const double *>(r.ws + r.off_partial), r.final_chunks, r.S_pad, s,
+                                  r.precision == COS_FP32_RESCALED
+                                      ? reinterpret_cast<const uint32_t *>(r.ws + r.off_maxbits)
+                                      : nullptr,
+                                  r.L, r.out, r.out_exp);
+        }
+        __syncthreads();  // LDS is reused by the group's next item
+    }
+}
+
+}  // namespace
+
+hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, const ServeReqDev *d_reqs,
+                                  hipGraphExec_t *exec) {
+    static std::atomic<bool> attr_set{false};
+    if (!attr_set.load(std::memory_order_acquire)) {
+        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(serve_fused_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        if (err != hipSuccess)
+            return err;
+        attr_set.store(true, std::memory_order_release);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t err = hipGraphCreate(&graph, 0);
+    if (err != hipSuccess)
+        return err;
+    hipGraphNode_t upload = nullptr, fused = nullptr, stream = nullptr;
+    err = hipGraphAddMemcpyNode1D(&upload, graph, nullptr, 0, d_tab, h_tab, sizeof(StepTable),
+                                  hipMemcpyHostToDevice);
+    const StepTable *tab_arg = d_tab;
+    const ServeReqDev *reqs_arg = d_reqs;
+    void *args[] = {&tab_arg, &reqs_arg};
+    if (err == hipSuccess) {
+        hipKernelNodeParams kp{};
+        kp.func = reinterpret_cast<void *>(serve_fused_kernel);
+        kp.gridDim = dim3(kServeFusedGrid);
+        kp.blockDim = dim3(kFusedThreads);
+        kp.sharedMemBytes = static_cast<unsigned>(kLdsBytes);
+        kp.kernelParams = args;
+        err = hipGraphAddKernelNode(&fused, graph, &upload, 1, &kp);
+    }
+    if (err == hipSuccess) {
+        hipKernelNodeParams kp{};
+        kp.func = reinterpret_cast<void *>(serve_stream_kernel);
+        kp.gridDim = dim3(kServeStreamGrid);
+        kp.blockDim = dim3(kBlock);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        err = hipGraphAddKernelNode(&stream, graph, &upload, 1, &kp);
+    }
+    if (err == hipSuccess)
+        err = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return err;
+}
+
+}  // namespace cosdag

@@ -1,0 +1,70 @@
+// Types shared by the serving runtime (server.cpp) and its step kernels
+// (serve.hip).
+#pragma once
+
+#include "cos_internal.h"
+
+namespace cosdag {
+
+// Work a request contributes to one step.
+enum ServeKind : uint32_t {
+    SK_FUSED = 0,    // the whole graph for 64-sample tiles, levels in LDS (one step per request)
+    SK_LEVEL = 1,    // one interior level: items = (row group of 32 rows) x (tile of 256 samples)
+    SK_FINAL = 2,    // final-node partial sums: items = (chunk of 256 edges) x (tile of 128 samples)
+    SK_COMBINE = 3,  // final-node combine: items = tiles of 256 samples
+};
+
+constexpr int kServeLevelK = 4;                            // samples per lane, level items
+constexpr int kServeLevelRows = 8;                         // rows per wave, level items
+constexpr int kServeLevelRowsPerItem = 4 * kServeLevelRows;  // 4 waves per streamed-kernel workgroup
+constexpr int kServeFinalK = 2;                            // samples per lane, final-node items
+constexpr int kServeCombineTile = kBlock;                  // samples per combine item
+constexpr int kServeMaxEntries = 512;                      // requests per step (upper bound on slots)
+
+// One admitted request as the step kernels see it (device copy per slot).
+struct ServeReqDev {
+    const int32_t *row_ptr;
+    const EdgeRec *edges;
+    const LevelDev *levels;
+    const double *x;
+    double *out;
+    int32_t *out_exp;
+    char *ws;                 // workspace of a streamed request (level buffers, exponents, partials)
+    int64_t S;
+    int64_t S_pad;
+    uint64_t off_buf0, off_buf1, off_maxbits, off_partial;
+    int32_t L;
+    int32_t precision;        // cos_precision
+    int32_t rows_variant;     // fused requests: rows per wave (compile-time variant)
+    int32_t final_chunks;     // streamed requests: final-node partial rows
+    uint32_t off_red, off_part;  // fused requests: LDS layout (one sample per lane)
+    int32_t pad[2];
+};
+
+struct StepEntry {
+    uint32_t slot;
+    uint32_t kind;        // ServeKind
+    uint32_t level;       // SK_LEVEL: the level l
+    uint32_t n_items;
+    uint32_t item_base;   // items of earlier entries of the same section
+    uint32_t n_rg;        // SK_LEVEL: row groups; SK_FINAL: chunks
+    uint32_t pad[2];
+};
+
+// Entries [0, n_fused) are whole-graph (fused) work, entries
+// [n_fused, n_fused + n_streamed) level / final / combine work; each section
+// numbers its items from 0.
+struct StepTable {
+    uint32_t n_fused, items_fused;
+    uint32_t n_streamed, items_streamed;
+    uint32_t pad[4];
+    StepEntry e[kServeMaxEntries];
+};
+
+// Build the executable graph of one step: upload of the host table h_tab to
+// d_tab, then the fused-work and streamed-work kernels as two independent
+// branches reading d_tab and the slot table d_reqs.
+hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, const ServeReqDev *d_reqs,
+                                  hipGraphExec_t *exec);
+
+}  // namespace cosdag

@@ -1,0 +1,591 @@
+// Serving runtime: admission by slot and HBM footprint, continuous batching of
+// level-synchronous steps, latency stamps (cos_server_* in cos.h).
+//
+// One scheduling thread owns all device work of a server.  A step is a replay
+// of an instantiated graph (step-table upload, then the whole-graph and the
+// streamed step kernels side by side) followed by a host callback; two step
+// tables alternate so the thread can queue step k+1 while
+// step k runs (stream order keeps every request's stages in sequence).  The
+// callback, which must not call HIP, only marks the requests that finished in
+// its step and wakes the thread.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "fused_plan.h"
+#include "serve_types.h"
+
+namespace cosdag {
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over [0, size) with coalescing, 256-byte granules.
+class Arena {
+  public:
+    explicit Arena(uint64_t size) : size_(size) {
+        if (size)
+            free_.push_back({0, size});
+    }
+    bool alloc(uint64_t n, uint64_t *off) {
+        n = static_cast<uint64_t>(round_up(static_cast<int64_t>(std::max<uint64_t>(n, 1)), 256));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                it->first += n;
+                it->second -= n;
+                if (it->second == 0)
+                    free_.erase(it);
+                used_ += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n) {
+        n = static_cast<uint64_t>(round_up(static_cast<int64_t>(std::max<uint64_t>(n, 1)), 256));
+        used_ -= n;
+        auto it = free_.begin();
+        while (it != free_.end() && it->first < off)
+            ++it;
+        it = free_.insert(it, {off, n});
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+
+  private:
+    uint64_t size_;
+    uint64_t used_ = 0;
+    std::list<std::pair<uint64_t, uint64_t>> free_;  // (offset, bytes), sorted by offset
+};
+
+enum ReqState { RS_QUEUED, RS_ACTIVE, RS_DONE, RS_CANCELED, RS_FAILED };
+
+struct Request {
+    uint64_t ticket = 0;
+    const Graph *g = nullptr;
+    const double *x = nullptr;
+    double *out = nullptr;
+    int32_t *out_exp = nullptr;
+    int64_t S = 0;
+    cos_precision p = COS_FP64;
+    bool fused = false;
+    FusedLayout flay;
+    Workspace wlay;
+    uint64_t footprint = 0, arena_off = 0;
+    int slot = -1;
+    int next_stage = 0, n_stages = 0;  // stages issued so far / in total
+    int steps = 0;
+    int64_t first_step = -1;
+    int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    ReqState state = RS_QUEUED;
+    cos_status status = COS_EAGAIN;
+};
+
+struct StepBuf {
+    StepTable *h_tab = nullptr;     // pinned
+    StepTable *d_tab = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool busy = false;
+    std::vector<Request *> finishing;  // requests whose last stage is in this step
+    struct Server *srv = nullptr;
+};
+
+}  // namespace
+}  // namespace cosdag
+
+struct cos_server {
+    cosdag::Request *dummy = nullptr;
+};
+
+namespace cosdag {
+namespace {
+
+struct Server : cos_server {
+    int device = 0;
+    uint64_t budget = 0;
+    int max_slots = 0;
+    std::vector<const Graph *> graphs;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::vector<Request *> slots;
+    Arena arena{0};
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int inflight = 0;
+    cos_server_stats st{};
+    // device
+    hipStream_t stream = nullptr;
+    char *d_arena = nullptr;
+    ServeReqDev *d_reqs = nullptr;
+    ServeReqDev *h_reqs = nullptr;  // pinned staging, one entry per slot
+    StepBuf bufs[2];
+    std::thread worker;
+
+    ~Server();
+    void run();
+};
+
+void step_done(void *p) {
+    StepBuf *b = static_cast<StepBuf *>(p);
+    Server *s = b->srv;
+    const int64_t t = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Request *r : b->finishing) {
+            if (r->state != RS_ACTIVE)
+                continue;  // failed while this step was in flight
+            r->t_done = t;
+            r->state = RS_DONE;
+            r->status = COS_OK;
+            if (r->footprint)
+                s->arena.release(r->arena_off, r->footprint);
+            s->slots[r->slot] = nullptr;
+            ++s->st.completed;
+        }
+        b->finishing.clear();
+        b->busy = false;
+        --s->inflight;
+    }
+    s->cv.notify_all();
+}
+
+uint32_t stage_items(const Request &r, int stage, uint32_t *n_rg, uint32_t *kind, uint32_t *level) {
+    const Graph &g = *r.g;
+    if (r.fused) {
+        *kind = SK_FUSED;
+        *level = 0;
+        *n_rg = 1;
+        return static_cast<uint32_t>((r.S + kWave - 1) / kWave);
+    }
+    const int L = g.L;
+    if (stage < L - 1) {  // interior level stage + 1
+        const int l = stage + 1;
+        *kind = SK_LEVEL;
+        *level = static_cast<uint32_t>(l);
+        *n_rg = static_cast<uint32_t>((g.levels[l - 1].w_dst + kServeLevelRowsPerItem - 1) / kServeLevelRowsPerItem);
+        return *n_rg * static_cast<uint32_t>(r.wlay.S_pad / (kWave * kServeLevelK));
+    }
+    if (stage == L - 1) {
+        *kind = SK_FINAL;
+        *level = static_cast<uint32_t>(L);
+        *n_rg = static_cast<uint32_t>(r.wlay.final_chunks);
+        return *n_rg * static_cast<uint32_t>(r.wlay.S_pad / (kWave * kServeFinalK));
+    }
+    *kind = SK_COMBINE;
+    *level = static_cast<uint32_t>(L);
+    *n_rg = 1;
+    return static_cast<uint32_t>((r.S + kServeCombineTile - 1) / kServeCombineTile);
+}
+
+void Server::run() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        // ---- admission (host bookkeeping under the lock; device actions afterwards)
+        std::vector<Request *> admitted;
+        int free_slots = 0;
+        for (Request *r : slots)
+            free_slots += r == nullptr;
+        for (auto it = queue.begin(); it != queue.end() && free_slots > 0;) {
+            Request *r = *it;
+            uint64_t off = 0;
+            if (r->footprint && !arena.alloc(r->footprint, &off)) {
+                ++it;  // does not fit now; later requests may
+                continue;
+            }
+            r->arena_off = off;
+            r->slot = static_cast<int>(std::find(slots.begin(), slots.end(), nullptr) - slots.begin());
+            slots[r->slot] = r;
+            r->state = RS_ACTIVE;
+            r->t_admit = now_ns();
+            --free_slots;
+            admitted.push_back(r);
+            it = queue.erase(it);
+        }
+        int active = 0;
+        for (Request *r : slots)
+            active += r != nullptr;
+        st.max_active = std::max<int64_t>(st.max_active, active);
+        st.peak_bytes = std::max<uint64_t>(st.peak_bytes, arena.used());
+
+        // ---- next step, if a table is free and some request has a stage left
+        StepBuf *b = nullptr;
+        int64_t step_index = -1;
+        for (StepBuf &cand : bufs)
+            if (!cand.busy) {
+                b = &cand;
+                break;
+            }
+        bool any_stage = false;
+        for (Request *r : slots)
+            any_stage |= r && r->next_stage < r->n_stages;
+        if (b && any_stage) {
+            // whole-graph (fused) entries first, then level / final / combine entries
+            StepTable &t = *b->h_tab;
+            uint32_t n = 0, items[2] = {0, 0}, count[2] = {0, 0};
+            for (int section = 0; section < 2; ++section) {
+                for (Request *r : slots) {
+                    if (!r || r->next_stage >= r->n_stages || r->fused != (section == 0))
+                        continue;
+                    StepEntry &e = t.e[n++];
+                    e.slot = static_cast<uint32_t>(r->slot);
+                    e.n_items = stage_items(*r, r->next_stage, &e.n_rg, &e.kind, &e.level);
+                    e.item_base = items[section];
+                    items[section] += e.n_items;
+                    ++count[section];
+                    if (r->first_step < 0)
+                        r->first_step = st.steps;
+                    ++r->steps;
+                    if (++r->next_stage == r->n_stages)
+                        b->finishing.push_back(r);
+                }
+            }
+            t.n_fused = count[0];
+            t.items_fused = items[0];
+            t.n_streamed = count[1];
+            t.items_streamed = items[1];
+            b->busy = true;
+            ++inflight;
+            step_index = st.steps++;
+            st.items += items[0] + items[1];
+            st.max_step_requests = std::max<int64_t>(st.max_step_requests, n);
+        } else {
+            b = nullptr;
+        }
+
+        if (admitted.empty() && !b) {
+            if (stop && queue.empty() && inflight == 0) {
+                bool idle = true;
+                for (Request *r : slots)
+                    idle &= r == nullptr;
+                if (idle)
+                    break;
+            }
+            cv.wait(lk);
+            continue;
+        }
+
+        // ---- device actions without the lock (the completion callback takes it)
+        lk.unlock();
+        hipError_t err = hipSuccess;
+        for (Request *r : admitted) {
+            const Graph &g = *r->g;
+            ServeReqDev &d = h_reqs[r->slot];
+            d = ServeReqDev{};
+            d.row_ptr = g.d_row_ptr;
+            d.edges = g.d_edges;
+            d.levels = g.d_levels;
+            d.x = r->x;
+            d.out = r->out;
+            d.out_exp = r->out_exp;
+            d.ws = r->footprint ? d_arena + r->arena_off : nullptr;
+            d.S = r->S;
+            d.S_pad = r->fused ? 0 : r->wlay.S_pad;
+            d.off_buf0 = r->wlay.off_buf0;
+            d.off_buf1 = r->wlay.off_buf1;
+            d.off_maxbits = r->wlay.off_maxbits;
+            d.off_partial = r->wlay.off_partial;
+            d.L = g.L;
+            d.precision = r->p;
+            d.rows_variant = rows_variant((g.max_width + kFusedWaves - 1) / kFusedWaves);
+            d.final_chunks = r->wlay.final_chunks;
+            d.off_red = static_cast<uint32_t>(r->flay.off_red);
+            d.off_part = static_cast<uint32_t>(r->flay.off_part);
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(d_reqs + r->slot, &d, sizeof(ServeReqDev), hipMemcpyHostToDevice, stream);
+            if (err == hipSuccess && !r->fused && r->p == COS_FP32_RESCALED)
+                err = launch_fill_u32(reinterpret_cast<uint32_t *>(d.ws + d.off_maxbits), 0u,
+                                      static_cast<int64_t>(g.L + 1) * r->wlay.S_pad, stream);
+        }
+        if (b && err == hipSuccess) {
+            TimedLaunch tl(KK_SERVE, stream);
+            err = hipGraphLaunch(b->exec, stream);
+        }
+        if (b && err == hipSuccess)
+            err = hipLaunchHostFunc(stream, step_done, b);
+        lk.lock();
+        if (err != hipSuccess) {
+            // the device is unusable for this server: fail everything admitted
+            for (Request *&r : slots) {
+                if (!r)
+                    continue;
+                r->state = RS_FAILED;
+                r->status = COS_EDEVICE;
+                r->t_done = now_ns();
+                ++st.failed;
+                r = nullptr;
+            }
+            if (b) {
+                b->finishing.clear();
+                b->busy = false;
+                --inflight;
+            }
+        }
+        (void)step_index;
+    }
+}
+
+Server::~Server() {
+    for (StepBuf &b : bufs) {
+        if (b.exec)
+            (void)hipGraphExecDestroy(b.exec);
+        if (b.d_tab)
+            (void)hipFree(b.d_tab);
+        if (b.h_tab)
+            (void)hipHostFree(b.h_tab);
+    }
+    if (d_reqs)
+        (void)hipFree(d_reqs);
+    if (h_reqs)
+        (void)hipHostFree(h_reqs);
+    if (d_arena)
+        (void)hipFree(d_arena);
+    if (stream)
+        (void)hipStreamDestroy(stream);
+}
+
+Server *server_of(cos_server *s) { return static_cast<Server *>(s); }
+
+}  // namespace
+}  // namespace cosdag
+
+using namespace cosdag;
+
+extern "C" cos_status cos_server_create(uint64_t hbm_budget, int32_t max_slots, cos_server **out) {
+    if (!out)
+        return fail(COS_EINVAL, "cos_server_create: out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > kServeMaxEntries)
+        return fail(COS_EINVAL, "cos_server_create: max_slots must be in 1.." + std::to_string(kServeMaxEntries));
+    try {
+        auto s = std::make_unique<Server>();
+        s->budget = hbm_budget;
+        s->max_slots = max_slots;
+        s->slots.assign(max_slots, nullptr);
+        s->arena = Arena(hbm_budget);
+        s->st.budget_bytes = hbm_budget;
+        hipError_t err = hipGetDevice(&s->device);
+        if (err == hipSuccess)
+            err = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (err == hipSuccess && hbm_budget)
+            err = hipMalloc(reinterpret_cast<void **>(&s->d_arena), hbm_budget);
+        if (err == hipSuccess)
+            err = hipMalloc(reinterpret_cast<void **>(&s->d_reqs), sizeof(ServeReqDev) * max_slots);
+        if (err == hipSuccess)
+            err = hipHostMalloc(reinterpret_cast<void **>(&s->h_reqs), sizeof(ServeReqDev) * max_slots,
+                                hipHostMallocDefault);
+        for (StepBuf &b : s->bufs) {
+            b.srv = s.get();
+            if (err == hipSuccess)
+                err = hipHostMalloc(reinterpret_cast<void **>(&b.h_tab), sizeof(StepTable), hipHostMallocDefault);
+            if (err == hipSuccess)
+                err = hipMalloc(reinterpret_cast<void **>(&b.d_tab), sizeof(StepTable));
+            if (err == hipSuccess)
+                err = serve_build_step_graph(b.d_tab, b.h_tab, s->d_reqs, &b.exec);
+        }
+        if (err != hipSuccess)
+            return hip_fail(err, "cos_server_create");
+        Server *raw = s.get();
+        raw->worker = std::thread([raw] { raw->run(); });
+        *out = s.release();
+        return COS_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(COS_ENOMEM, "cos_server_create: host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(COS_EDEVICE, std::string("cos_server_create: ") + e.what());
+    }
+}
+
+extern "C" cos_status cos_server_add_graph(cos_server *h, const cos_graph *g, int32_t *gid) {
+    if (!h || !g || !gid)
+        return fail(COS_EINVAL, "cos_server_add_graph: NULL argument");
+    Server *s = server_of(h);
+    const Graph &G = graph_of(g);
+    if (G.device != s->device)
+        return fail(COS_EINVAL, "cos_server_add_graph: graph lives on another device");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->graphs.push_back(&G);
+    *gid = static_cast<int32_t>(s->graphs.size() - 1);
+    return COS_OK;
+}
+
+extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double *x_dev, int64_t S, cos_precision p,
+                                        double *out_dev, int32_t *out_exp_dev, uint64_t *ticket) {
+    if (!h || !x_dev || !out_dev || !ticket)
+        return fail(COS_EINVAL, "cos_server_submit: NULL argument");
+    if (p != COS_FP64 && p != COS_FP32_RESCALED && p != COS_FP32)
+        return fail(COS_EINVAL, "cos_server_submit: unknown precision");
+    if (S < 1 || S > INT32_MAX)
+        return fail(COS_EINVAL, "cos_server_submit: S must be in 1..2^31-1");
+    Server *s = server_of(h);
+    auto r = std::make_unique<Request>();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (gid < 0 || gid >= static_cast<int32_t>(s->graphs.size()))
+            return fail(COS_EINVAL, "cos_server_submit: unknown graph id");
+        r->g = s->graphs[gid];
+    }
+    const Graph &g = *r->g;
+    r->x = x_dev;
+    r->out = out_dev;
+    r->out_exp = out_exp_dev;
+    r->S = S;
+    r->p = p;
+    // the same plan choice cos_evaluate makes for this graph (results are bit-identical to it)
+    r->fused = g.path == COS_PATH_FUSED || (g.path == COS_PATH_AUTO && fused_fits(g, p));
+    if (r->fused) {
+        if (!fused_fits(g, p))
+            return fail(COS_EINVAL, "cos_server_submit: fused plan requested but the graph does not fit in LDS");
+        r->flay = fused_layout(g, p == COS_FP64 ? sizeof(double) : sizeof(float), p == COS_FP32_RESCALED, 1);
+        r->n_stages = 1;
+    } else {
+        if (max_chunk(g, p) < S)
+            return fail(COS_EINVAL, "cos_server_submit: S too large for one sweep; use cos_evaluate");
+        r->wlay = layout_for_chunk(g, S, p);
+        r->footprint = r->wlay.bytes;
+        r->n_stages = g.L + 1;
+        if (r->footprint > s->budget)
+            return fail(COS_ENOMEM, "cos_server_submit: the request's workspace (" + std::to_string(r->footprint) +
+                                        " bytes) exceeds the server's HBM budget");
+    }
+    r->t_submit = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop)
+            return fail(COS_EINVAL, "cos_server_submit: server is shutting down");
+        r->ticket = s->next_ticket++;
+        *ticket = r->ticket;
+        s->queue.push_back(r.get());
+        s->reqs.emplace(r->ticket, std::move(r));
+        ++s->st.submitted;
+    }
+    s->cv.notify_all();
+    return COS_OK;
+}
+
+namespace {
+cos_status finish_poll(Server *s, std::unordered_map<uint64_t, std::unique_ptr<Request>>::iterator it,
+                       cos_req_stats *out) {
+    Request *r = it->second.get();
+    if (out) {
+        out->t_submit_ns = r->t_submit;
+        out->t_admit_ns = r->t_admit;
+        out->t_done_ns = r->t_done;
+        out->status = r->status;
+        out->steps = r->steps;
+        out->first_step = r->first_step;
+        out->footprint = static_cast<int64_t>(r->footprint);
+    }
+    if (r->state == RS_QUEUED || r->state == RS_ACTIVE)
+        return COS_EAGAIN;
+    const cos_status st = r->status;
+    bool referenced = false;  // a failed request may still be listed by a step in flight
+    for (const StepBuf &b : s->bufs)
+        referenced |= std::find(b.finishing.begin(), b.finishing.end(), r) != b.finishing.end();
+    if (!referenced)
+        s->reqs.erase(it);
+    return st;
+}
+}  // namespace
+
+extern "C" cos_status cos_server_poll(cos_server *h, uint64_t ticket, cos_req_stats *stats) {
+    if (!h)
+        return fail(COS_EINVAL, "cos_server_poll: server is NULL");
+    Server *s = server_of(h);
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end())
+        return fail(COS_EINVAL, "cos_server_poll: unknown ticket");
+    return finish_poll(s, it, stats);
+}
+
+extern "C" cos_status cos_server_wait(cos_server *h, uint64_t ticket, cos_req_stats *stats) {
+    if (!h)
+        return fail(COS_EINVAL, "cos_server_wait: server is NULL");
+    Server *s = server_of(h);
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end())
+        return fail(COS_EINVAL, "cos_server_wait: unknown ticket");
+    Request *r = it->second.get();
+    s->cv.wait(lk, [r] { return r->state != RS_QUEUED && r->state != RS_ACTIVE; });
+    return finish_poll(s, s->reqs.find(ticket), stats);
+}
+
+extern "C" cos_status cos_server_cancel(cos_server *h, uint64_t ticket) {
+    if (!h)
+        return fail(COS_EINVAL, "cos_server_cancel: server is NULL");
+    Server *s = server_of(h);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end())
+            return fail(COS_EINVAL, "cos_server_cancel: unknown ticket");
+        Request *r = it->second.get();
+        if (r->state != RS_QUEUED)
+            return r->state == RS_ACTIVE ? COS_EAGAIN : COS_OK;
+        s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+        r->state = RS_CANCELED;
+        r->status = COS_ECANCELED;
+        r->t_done = now_ns();
+        ++s->st.cancelled;
+    }
+    s->cv.notify_all();
+    return COS_OK;
+}
+
+extern "C" cos_status cos_server_get_stats(cos_server *h, cos_server_stats *out) {
+    if (!h || !out)
+        return fail(COS_EINVAL, "cos_server_get_stats: NULL argument");
+    Server *s = server_of(h);
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    return COS_OK;
+}
+
+extern "C" cos_status cos_server_destroy(cos_server *h) {
+    if (!h)
+        return COS_OK;
+    Server *s = server_of(h);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (Request *r : s->queue) {
+            r->state = RS_CANCELED;
+            r->status = COS_ECANCELED;
+            ++s->st.cancelled;
+        }
+        s->queue.clear();
+    }
+    s->cv.notify_all();
+    if (s->worker.joinable())
+        s->worker.join();
+    hipError_t err = hipStreamSynchronize(s->stream);
+    delete s;
+    if (err != hipSuccess)
+        return hip_fail(err, "cos_server_destroy");
+    return COS_OK;
+}

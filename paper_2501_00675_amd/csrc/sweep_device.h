@@ -234,9 +234,7 @@ __device__ __forceinline__ void final_quarter_lds(const EdgeRec *__restrict__ ed
 
 // ---------------------------------------------------------------- fused sweep
 
-constexpr int kFusedWaves = 16;
 constexpr int kFusedThreads = kFusedWaves * kWave;
-constexpr int kQuarter = kFinalChunk / 4;
 
 // Everything a workgroup needs to sweep one graph for one tile in LDS.
 struct FusedGraph {

@@ -99,6 +99,25 @@ def test_evaluate_rejects_null_and_bad_args():
     assert L.LIB.cos_timing_read(99, ctypes.byref(ms), ctypes.byref(n)) == -1
 
 
+def test_server_rejects_null_and_bad_args():
+    # argument checks that come before any device call
+    import paper_2501_00675_amd._lib as L
+
+    h = ctypes.c_void_p()
+    for slots in (0, -1, 513):
+        assert L.LIB.cos_server_create(1 << 20, slots, ctypes.byref(h)) == -1
+        assert "max_slots" in L.LIB.cos_last_error().decode() and not h.value
+    assert L.LIB.cos_server_create(1 << 20, 4, None) == -1
+    gid, t = ctypes.c_int32(), ctypes.c_uint64()
+    assert L.LIB.cos_server_add_graph(None, None, ctypes.byref(gid)) == -1
+    assert L.LIB.cos_server_submit(None, 0, None, 4, 0, None, None, ctypes.byref(t)) == -1
+    assert L.LIB.cos_server_poll(None, 1, None) == -1
+    assert L.LIB.cos_server_wait(None, 1, None) == -1
+    assert L.LIB.cos_server_cancel(None, 1) == -1
+    assert L.LIB.cos_server_get_stats(None, None) == -1
+    assert L.LIB.cos_server_destroy(None) == 0
+
+
 def test_no_cpu_fallback_in_product_path():
     # the package never imports the oracle and has no torch compute on the path
     pkg = os.path.join(ROOT, "paper_2501_00675_amd")

@@ -20,6 +20,8 @@ fanned out with SeedSequence.spawn into structure / parameter / sample streams.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -78,8 +80,8 @@ def serving_mix(n_graphs: int | None = None, n_requests: int | None = None, seed
         cfg["n_requests"] = n_requests
     sd = cfg["seed"] if seed is None else seed
     ss_g, ss_r = np.random.SeedSequence(sd).spawn(2)
-    graphs = []
-    for i, ss in enumerate(ss_g.spawn(cfg["n_graphs"])):
+
+    def one_graph(i, ss):
         rng = np.random.Generator(np.random.PCG64(ss))
         L = int(rng.integers(cfg["L"][0], cfg["L"][1] + 1))
         W = int(_log_uniform_int(rng, *cfg["width"]))
@@ -89,7 +91,11 @@ def serving_mix(n_graphs: int | None = None, n_requests: int | None = None, seed
         g = layered_graph([1] + [W] * (L - 1) + [1], d, rng)
         draw_params(g, rng, b_range=cfg["b"])
         g.meta = dict(config="serving", graph=i, L=L, width=W, degree=d)
-        graphs.append(g)
+        return g
+
+    # every graph has its own seed stream, so building them in threads changes nothing
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        graphs = list(ex.map(one_graph, range(cfg["n_graphs"]), ss_g.spawn(cfg["n_graphs"])))
     rng = np.random.Generator(np.random.PCG64(ss_r))
     reqs = []
     for r in range(cfg["n_requests"]):
