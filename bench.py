@@ -51,9 +51,9 @@ def level_bytes(g, S_pad: int, precision: str) -> list:
     rows once, write this level's rows once, read the edge records and row
     pointers once, read x once (S samples, 3 x float64)."""
     B = 8 if precision == "fp64" else 4
-    # record fields a launch needs: src (4 B), the five denominator coefficients (binary64) and a
-    # (binary64 for FP64, binary32 for the FP32 paths)
-    rec = 4 + 5 * 8 + (8 if precision == "fp64" else 4)
+    # record fields a launch needs: binary64 sweeps src (4 B) + c0, cb, g0, g1, g2, a (6 x 8 B);
+    # binary32 sweeps src (4 B) + a, b, k0, k1, k2 (5 x 4 B)
+    rec = 4 + 6 * 8 if precision == "fp64" else 4 + 5 * 4
     out = []
     for l in range(1, g.L):
         w_prev = 0 if l == 1 else int(g.widths[l - 1])  # level 1 reads the root's constant 1
@@ -176,23 +176,45 @@ def roofline(g, S_pad, precision, kern, steps, workload):
     else:
         r = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "kernel": dom}
     r["traffic"] = profiled_traffic(r.get("kernel"), workload, precision)
+    r["kernel_src_id"] = kernel_source_id(r.get("kernel"))
     return r
+
+
+# sources that define each timed kernel and its launch (device code, launcher, planner, build flags)
+KERNEL_SOURCES = {
+    "level_gather_kernel": ["kernels_level.hip", "sweep_device.h", "kernels_common.h", "cos_internal.h",
+                            "evaluate.cpp", "../_build.py"],
+    "fused_sweep_kernel": ["kernels_fused.hip", "fused_plan.h", "sweep_device.h", "kernels_common.h",
+                           "cos_internal.h", "evaluate.cpp", "../_build.py"],
+}
+
+
+def kernel_source_id(kernel):
+    """Hash of the sources a kernel is built and launched from (changes whenever the kernel can change)."""
+    import hashlib
+
+    files = KERNEL_SOURCES.get(kernel)
+    if not files:
+        return None
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2501_00675_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def profiled_traffic(kernel, workload, precision):
     """HBM bytes per launch from the committed rocprofv3 --pmc summaries (FETCH_SIZE and WRITE_SIZE in KiB
     per dispatch, scaled by the factors a plain copy kernel gives), or None when no summary exists for this
-    kernel and workload or the library was rebuilt since the counters were taken."""
-    import paper_2501_00675_amd as P
-
-    build = P.LIB.cos_build_id().decode()
+    kernel and workload or the kernel's sources changed since the counters were taken."""
+    src = kernel_source_id(kernel)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             if not line.startswith("pmc:"):
                 continue
             kv = dict(item.split("=", 1) for item in line[4:].split())
             if (kv.get("kernel") == kernel and kv.get("workload") == workload and kv.get("precision") == precision
-                    and kv.get("build_id") == build):
+                    and src is not None and kv.get("src_id") == src):
                 return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"])
                                  + float(kv["write_kib"]) * float(kv["write_scale"]))
     return None
@@ -265,6 +287,9 @@ def serving_leg(P, args):
     def batched(precision, arrivals_ns, n=None):
         n = len(reqs) if n is None else n
         before = srv.stats()
+        P.timing_read("serve")
+        P.timing_read("fill")
+        P.timing_enable(True)
         t0 = time.monotonic_ns() + 1_000_000
         tickets = []
         for i in range(n):
@@ -275,11 +300,14 @@ def serving_leg(P, args):
                                       sync_inputs=False))
         st = [srv.wait(t) for t in tickets]
         after = srv.stats()
+        P.timing_enable(False)
+        step_ms, n_steps = P.timing_read("serve")
         done = np.array([d["t_done_ns"] for d in st], np.float64)
         lat = (done - (t0 + np.asarray(arrivals_ns[:n], np.float64))) / 1e6
         span = (done.max() - t0) / 1e9
         return {"value": float(es[:n].sum()) / span, "makespan_ms": span * 1e3, "p50_ms": _pct(lat, 50),
                 "p99_ms": _pct(lat, 99), "steps": after["steps"] - before["steps"],
+                "step_graph_ms": step_ms, "mean_step_us": 1000.0 * step_ms / max(n_steps, 1),
                 "max_step_requests": after["max_step_requests"], "max_active": after["max_active"],
                 "peak_workspace_bytes": after["peak_bytes"]}
 

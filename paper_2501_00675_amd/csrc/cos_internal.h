@@ -23,15 +23,26 @@ struct alignas(16) EdgeRec {
     double c0, cb, g0, g1, g2;
     double a;
     int32_t src;        // index of the source node within the previous level
-    float a32;          // a rounded to binary32 (nearest even)
+    int32_t unused;
     int32_t row_end;    // 1 if this is the last edge into its destination node
     int32_t zero_rows;  // nodes without in-edges that directly follow that destination
 };
 static_assert(sizeof(EdgeRec) == 64, "EdgeRec layout");
 
-// The device edge array carries this many zeroed records after the last edge,
+// Binary32 edge record (32 bytes) read by the binary32 level sweeps: a, b and
+// k rounded to binary32 (nearest even), the factor being formed directly as
+// a / (1 + b |x - k|^2) in binary32; same source index and row flags as EdgeRec.
+struct alignas(16) EdgeRec32 {
+    float a, b, k0, k1, k2;
+    int32_t src;
+    int32_t row_end;
+    int32_t zero_rows;
+};
+static_assert(sizeof(EdgeRec32) == 32, "EdgeRec32 layout");
+
+// The device edge arrays carry this many zeroed records after the last edge,
 // so that kernels may fetch records in fixed-size chunks without bounds tests.
-constexpr int kEdgePad = 4;
+constexpr int kEdgePad = 8;
 
 // Per edge level l = 1..L (stored at index l-1).
 struct LevelDesc {
@@ -66,7 +77,8 @@ struct Graph {
     void *d_base = nullptr;
     size_t d_bytes = 0;
     int32_t *d_row_ptr = nullptr;     // global edge indices, per level w_dst+1 entries
-    EdgeRec *d_edges = nullptr;
+    EdgeRec *d_edges = nullptr;       // binary64 records (binary64 sweeps, every final node)
+    EdgeRec32 *d_edges32 = nullptr;   // binary32 records (interior levels of the binary32 sweeps)
     LevelDev *d_levels = nullptr;     // L entries
     int device = 0;
     cos_path path = COS_PATH_AUTO;    // kernel plan chosen by cos_graph_set_path

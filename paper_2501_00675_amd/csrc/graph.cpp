@@ -255,6 +255,7 @@ extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const i
         // per-level CSR over destinations (global edge indices) and edge records
         std::vector<int32_t> row_ptr(rp);
         std::vector<EdgeRec> recs(n_edges + kEdgePad, EdgeRec{});
+        std::vector<EdgeRec32> recs32(n_edges + kEdgePad, EdgeRec32{});
         std::vector<LevelDev> ldev(L);
         for (int32_t l = 1; l <= L; ++l) {
             LevelDesc &d = G.levels[l - 1];
@@ -284,9 +285,18 @@ extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const i
                 rec.g2 = -2.0 * b * k2;
                 rec.a = G.h_a[q];
                 rec.src = static_cast<int32_t>(G.h_src[q] - sfirst);
-                rec.a32 = static_cast<float>(G.h_a[q]);
+                rec.unused = 0;
                 rec.row_end = 0;
                 rec.zero_rows = 0;
+                EdgeRec32 &r32 = recs32[q];
+                r32.a = static_cast<float>(G.h_a[q]);
+                r32.b = static_cast<float>(b);
+                r32.k0 = static_cast<float>(k0);
+                r32.k1 = static_cast<float>(k1);
+                r32.k2 = static_cast<float>(k2);
+                r32.src = rec.src;
+                r32.row_end = 0;
+                r32.zero_rows = 0;
             }
             // row boundaries inside the edge stream: the last edge of every
             // non-empty row, and how many empty rows follow it
@@ -299,15 +309,18 @@ extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const i
                 while (z < d.w_dst && r[z + 1] == r[z])
                     ++z;
                 last.zero_rows = static_cast<int32_t>(z - (j + 1));
+                recs32[r[j + 1] - 1].row_end = 1;
+                recs32[r[j + 1] - 1].zero_rows = last.zero_rows;
             }
             ldev[l - 1] = LevelDev{static_cast<int32_t>(d.w_dst), static_cast<int32_t>(d.rp_begin),
                                    static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges)};
         }
 
-        // one device allocation: row_ptr | edge records | level table
+        // one device allocation: row_ptr | edge records | binary32 edge records | level table
         const size_t off_rp = 0;
         const size_t off_rec = round_up(rp * sizeof(int32_t), 256);
-        const size_t off_lev = off_rec + round_up((n_edges + kEdgePad) * sizeof(EdgeRec), 256);
+        const size_t off_rec32 = off_rec + round_up((n_edges + kEdgePad) * sizeof(EdgeRec), 256);
+        const size_t off_lev = off_rec32 + round_up((n_edges + kEdgePad) * sizeof(EdgeRec32), 256);
         const size_t total = off_lev + round_up(L * sizeof(LevelDev), 256);
         hipError_t err = hipGetDevice(&G.device);
         if (err != hipSuccess)
@@ -319,10 +332,13 @@ extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const i
         char *base = static_cast<char *>(G.d_base);
         G.d_row_ptr = reinterpret_cast<int32_t *>(base + off_rp);
         G.d_edges = reinterpret_cast<EdgeRec *>(base + off_rec);
+        G.d_edges32 = reinterpret_cast<EdgeRec32 *>(base + off_rec32);
         G.d_levels = reinterpret_cast<LevelDev *>(base + off_lev);
         err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
         if (err == hipSuccess)
             err = hipMemcpy(G.d_edges, recs.data(), recs.size() * sizeof(EdgeRec), hipMemcpyHostToDevice);
+        if (err == hipSuccess)
+            err = hipMemcpy(G.d_edges32, recs32.data(), recs32.size() * sizeof(EdgeRec32), hipMemcpyHostToDevice);
         if (err == hipSuccess)
             err = hipMemcpy(G.d_levels, ldev.data(), L * sizeof(LevelDev), hipMemcpyHostToDevice);
         if (err != hipSuccess) {

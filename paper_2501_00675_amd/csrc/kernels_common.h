@@ -23,22 +23,14 @@ __device__ __forceinline__ double edge_factor64(const EdgeRec &e, double x0, dou
     return __builtin_fma(__builtin_fma(-D, w0, e.a), r, w0);
 }
 
-// binary32 factor: the denominator formed in binary64 and rounded once, then
-// v_rcp_f32 (1.5 ulp) and the product with a rounded to binary32.
-__device__ __forceinline__ float edge_factor32(const EdgeRec &e, double x0, double x1, double x2, double q) {
-    const float D = static_cast<float>(edge_denom(e, x0, x1, x2, q));
-    return e.a32 * __builtin_amdgcn_rcpf(D);
-}
-
-template <typename T>
-__device__ __forceinline__ T edge_factor(const EdgeRec &e, double x0, double x1, double x2, double q);
-template <>
-__device__ __forceinline__ double edge_factor<double>(const EdgeRec &e, double x0, double x1, double x2, double q) {
-    return edge_factor64(e, x0, x1, x2, q);
-}
-template <>
-__device__ __forceinline__ float edge_factor<float>(const EdgeRec &e, double x0, double x1, double x2, double q) {
-    return edge_factor32(e, x0, x1, x2, q);
+// binary32 factor from the binary32 record and the sample rounded to binary32:
+// r = x - k, D = 1 + b |r|^2 by fused multiply-adds, then v_rcp_f32 (1.5 ulp,
+// measured) and the product with a.  D >= 1 up to rounding, so the reciprocal
+// needs no scaling.
+__device__ __forceinline__ float edge_factor32(const EdgeRec32 &e, float x0, float x1, float x2) {
+    const float r0 = x0 - e.k0, r1 = x1 - e.k1, r2 = x2 - e.k2;
+    const float s = __builtin_fmaf(r2, r2, __builtin_fmaf(r1, r1, r0 * r0));
+    return e.a * __builtin_amdgcn_rcpf(__builtin_fmaf(e.b, s, 1.0f));
 }
 
 // ilogb of a non-negative binary32 given by its bit pattern; 0, inf and NaN

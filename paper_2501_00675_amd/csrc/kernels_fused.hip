@@ -43,7 +43,7 @@ hipError_t launch_fused_t(const Graph &g, const double *x, int64_t S, double *ou
             attr_set.store(true, std::memory_order_release);
         }
         const FusedLayout f = fused_layout(g, sizeof(T), RESCALE, K);
-        const FusedGraph G{g.d_row_ptr, g.d_edges, g.d_levels, g.L, x, S, out, out_exp};
+        const FusedGraph G{g.d_row_ptr, g.d_edges, g.d_edges32, g.d_levels, g.L, x, S, out, out_exp};
         const dim3 grid(static_cast<unsigned>((S + kWave * K - 1) / (kWave * K)));
         TimedLaunch tl(KK_FUSED, s);
         hipLaunchKernelGGL(kern, grid, dim3(kFusedThreads), f.total, s, G, static_cast<uint32_t>(f.off_red),

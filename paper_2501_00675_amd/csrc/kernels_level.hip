@@ -38,7 +38,11 @@ namespace {
 // xcd_group = 0: tile-major order, so the whole GPU works on one tile at a
 // time and the tile's slice of the previous level stays in the memory-side
 // Infinity Cache while every XCD gathers from it.
-__device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group, int &tile, int &rg) {
+// reverse_tiles (tile-major order only): the launch walks the tiles from the
+// last to the first, so that it starts on the slice the previous level wrote
+// last, which is the one most likely still in the Infinity Cache.
+__device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group, int reverse_tiles, int &tile,
+                                           int &rg) {
     if (xcd_group) {
         const int xcd = static_cast<int>(blockIdx.x % kXcds);
         const int local = static_cast<int>(blockIdx.x / kXcds);
@@ -48,6 +52,8 @@ __device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group,
     } else {
         tile = static_cast<int>(blockIdx.x) / n_rg;
         rg = static_cast<int>(blockIdx.x) - tile * n_rg;
+        if (reverse_tiles)
+            tile = n_tiles - 1 - tile;
     }
     return tile < n_tiles;
 }
@@ -61,17 +67,17 @@ __device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group,
 // largest |value| of this level is folded into cur_max[s].
 template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE>
 __global__ __launch_bounds__(kBlock) void level_gather_kernel(
-    const int32_t *__restrict__ row_ptr, const EdgeRec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
-    int32_t n_tiles, int32_t xcd_group, const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
+    const int32_t *__restrict__ row_ptr, const typename SweepPath<T>::Rec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
+    int32_t n_tiles, int32_t xcd_group, int32_t reverse_tiles, const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
     const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
     uint32_t *__restrict__ cur_max) {
     int tile, rg;
-    if (!block_tile(n_rg, n_tiles, xcd_group, tile, rg))
+    if (!block_tile(n_rg, n_tiles, xcd_group, reverse_tiles, tile, rg))
         return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
-    LaneSamples<K> smp;
+    typename SweepPath<T>::template Samples<K> smp;
     smp.load(x, S, xs, tbase, lane);
     int esh[K];
     uint32_t lmax[K];
@@ -138,6 +144,7 @@ constexpr int kRows = 8;      // consecutive rows per wave in the interior-level
 constexpr int kK = 4;         // samples per lane (interior levels)
 constexpr int kKFinal = 2;    // samples per lane (final node)
 constexpr int64_t kL2Slice = 1 << 20;  // a tile slice up to this size is kept in one XCD's L2
+constexpr bool kAlternateTiles = true;  // tile-major launches alternate their tile order level by level
 
 template <typename T, bool RESCALE>
 hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
@@ -147,22 +154,28 @@ hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, in
     const int64_t n_rg = (d.w_dst + rows_per_group - 1) / rows_per_group;
     const int64_t n_tiles = ld / (kWave * kK);
     const int32_t xcd_group = d.w_src * kWave * kK * static_cast<int64_t>(sizeof(T)) <= kL2Slice ? 1 : 0;
+    const int32_t reverse_tiles = kAlternateTiles && (l & 1) == 0 ? 1 : 0;
     const int64_t grid = (xcd_group ? round_up(n_tiles, kXcds) : n_tiles) * n_rg;
     if (grid <= 0)
         return hipSuccess;
     if (grid > INT32_MAX)
         return hipErrorInvalidConfiguration;
     const int32_t *rp = g.d_row_ptr + d.rp_begin;
+    const typename SweepPath<T>::Rec *recs;
+    if constexpr (sizeof(T) == sizeof(double))
+        recs = g.d_edges;
+    else
+        recs = g.d_edges32;
     TimedLaunch tl(KK_LEVEL, s);
     if (prev == nullptr)
         hipLaunchKernelGGL((level_gather_kernel<T, kK, kRows, true, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
-                           g.d_edges, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
-                           static_cast<int32_t>(n_tiles), xcd_group, nullptr, static_cast<T *>(cur), ld, x, S, xs,
+                           recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
+                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, nullptr, static_cast<T *>(cur), ld, x, S, xs,
                            prev_max, cur_max);
     else
         hipLaunchKernelGGL((level_gather_kernel<T, kK, kRows, false, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
-                           g.d_edges, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
-                           static_cast<int32_t>(n_tiles), xcd_group, static_cast<const T *>(prev),
+                           recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
+                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, static_cast<const T *>(prev),
                            static_cast<T *>(cur), ld, x, S, xs, prev_max, cur_max);
     return hipGetLastError();
 }

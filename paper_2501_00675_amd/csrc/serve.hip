@@ -41,7 +41,7 @@ template <typename T, int RMAX, bool RESCALE>
 __device__ __forceinline__ void serve_fused(const ServeReqDev &r, uint32_t tile, unsigned char *lds, int wave,
                                             int lane) {
     if constexpr (acc_fits(sizeof(T), 1, RMAX)) {
-        const FusedGraph G{r.row_ptr, r.edges, r.levels, r.L, r.x, r.S, r.out, r.out_exp};
+        const FusedGraph G{r.row_ptr, r.edges, r.edges32, r.levels, r.L, r.x, r.S, r.out, r.out_exp};
         fused_tile<T, 1, RMAX, RESCALE>(G, static_cast<int64_t>(tile) * kWave, reinterpret_cast<T *>(lds),
                                         reinterpret_cast<uint32_t *>(lds + r.off_red),
                                         reinterpret_cast<double *>(lds + r.off_part), wave, lane);
@@ -82,14 +82,19 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     const uint32_t rg = local % n_rg;
     const uint32_t tile = local / n_rg;
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
-    const LevelDev lv = r.levels[l - 1];
+    const LevelDev lv = load_level(r.levels, l - 1);
     T *const b0 = reinterpret_cast<T *>(r.ws + r.off_buf0);
     T *const b1 = reinterpret_cast<T *>(r.ws + r.off_buf1);
     T *cur = (l - 1) & 1 ? b1 : b0;
     const T *prev = (l - 2) & 1 ? b1 : b0;
     uint32_t *maxbits = reinterpret_cast<uint32_t *>(r.ws + r.off_maxbits);
-    LaneSamples<K> smp;
+    typename SweepPath<T>::template Samples<K> smp;
     smp.load(r.x, r.S, r.S, tbase, lane);
+    const typename SweepPath<T>::Rec *recs;
+    if constexpr (sizeof(T) == sizeof(double))
+        recs = r.edges;
+    else
+        recs = r.edges32;
     int esh[K];
     uint32_t lmax[K];
 #pragma unroll
@@ -102,10 +107,10 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     const int jend = min(jbeg + kServeLevelRows, lv.w_dst);
     const int32_t *rp = r.row_ptr + lv.rp_begin;
     if (l == 1)
-        level_wave_rows<T, K, true, RESCALE>(rp, r.edges, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
+        level_wave_rows<T, K, true, RESCALE>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
                                              lmax);
     else
-        level_wave_rows<T, K, false, RESCALE>(rp, r.edges, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
+        level_wave_rows<T, K, false, RESCALE>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
                                               lmax);
     if constexpr (RESCALE) {
         if (l <= r.L - 2)
@@ -122,7 +127,7 @@ __device__ __forceinline__ void serve_final(const ServeReqDev &r, uint32_t local
     const uint32_t n_chunks = static_cast<uint32_t>(r.final_chunks);
     const int c = static_cast<int>(local % n_chunks);
     const int64_t tbase = static_cast<int64_t>(local / n_chunks) * (kWave * K);
-    const LevelDev lf = r.levels[r.L - 1];
+    const LevelDev lf = load_level(r.levels, r.L - 1);
     LaneSamples<K> smp;
     smp.load(r.x, r.S, r.S, tbase, lane);
     const int c_end = min((c + 1) * kFinalChunk, lf.n_edges);

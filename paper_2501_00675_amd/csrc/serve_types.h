@@ -25,6 +25,7 @@ constexpr int kServeMaxEntries = 512;                      // requests per step 
 struct ServeReqDev {
     const int32_t *row_ptr;
     const EdgeRec *edges;
+    const EdgeRec32 *edges32;
     const LevelDev *levels;
     const double *x;
     double *out;
@@ -38,7 +39,6 @@ struct ServeReqDev {
     int32_t rows_variant;     // fused requests: rows per wave (compile-time variant)
     int32_t final_chunks;     // streamed requests: final-node partial rows
     uint32_t off_red, off_part;  // fused requests: LDS layout (one sample per lane)
-    int32_t pad[2];
 };
 
 struct StepEntry {

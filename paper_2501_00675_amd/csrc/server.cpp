@@ -297,6 +297,7 @@ void Server::run() {
             d = ServeReqDev{};
             d.row_ptr = g.d_row_ptr;
             d.edges = g.d_edges;
+            d.edges32 = g.d_edges32;
             d.levels = g.d_levels;
             d.x = r->x;
             d.out = r->out;

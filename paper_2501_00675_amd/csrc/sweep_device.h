@@ -12,9 +12,60 @@ namespace cosdag {
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// Edge records fetched per step of a stream (the edge array is padded by as
-// many zeroed records, so a full chunk can always be read).
-constexpr int kChunk = kEdgePad;
+// Edge records fetched per scalar wait: 256 bytes in a streamed level (four
+// binary64 or eight binary32 records), four in the whole-graph sweep and the
+// final node.  The record arrays are padded with kEdgePad zeroed records, so a
+// full chunk can always be read.
+constexpr int kChunk = 4;
+template <typename Rec>
+constexpr int kStreamChunk = 256 / static_cast<int>(sizeof(Rec));
+
+// The graph's device arrays (row pointers, edge records, level table) are
+// written once when the graph is created and only read by kernels, so they are
+// read through the constant address space: the compiler then treats a fetch
+// from a wave-uniform address as a uniform scalar load wherever the pointer came
+// from (a pointer read from memory is otherwise generic, and loads through it
+// count as per-lane).
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ ConstPtr<T> as_const(const T *p) {
+    return (ConstPtr<T>)(p);
+}
+
+// Level table entry i (fields read one by one: a struct cannot be copied
+// through an address-space-qualified reference).
+__device__ __forceinline__ LevelDev load_level(const LevelDev *levels, int i) {
+    static_assert(sizeof(LevelDev) == 4 * sizeof(int32_t), "four int32 fields");
+    const ConstPtr<int32_t> p = as_const(reinterpret_cast<const int32_t *>(levels)) + 4 * i;
+    return LevelDev{p[0], p[1], p[2], p[3]};
+}
+
+// Fetch C consecutive records (C * sizeof(Rec) = 128 or 256 bytes) into scalar
+// registers at once.  The empty asm takes every 16-byte piece as an SGPR
+// operand, so all pieces are loaded (one scalar wait) before any field is
+// used; left alone, the compiler fetches each field next to its first use, one
+// dependent round trip per edge.
+template <int C, typename Rec>
+__device__ __forceinline__ void load_chunk(const Rec *p, Rec (&r)[C]) {
+    static_assert(C <= kEdgePad, "a chunk starting at the last edge must stay inside the padded array");
+    using V4 = __attribute__((ext_vector_type(4))) unsigned;
+    constexpr int kBytes = C * static_cast<int>(sizeof(Rec));
+    static_assert(kBytes == 128 || kBytes == 256, "chunks of 128 or 256 bytes");
+    const ConstPtr<V4> q = (ConstPtr<V4>)(as_const(p));
+    V4 a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3], a4 = q[4], a5 = q[5], a6 = q[6], a7 = q[7];
+    if constexpr (kBytes == 256) {
+        V4 b0 = q[8], b1 = q[9], b2 = q[10], b3 = q[11], b4 = q[12], b5 = q[13], b6 = q[14], b7 = q[15];
+        asm volatile("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3), "+s"(a4), "+s"(a5), "+s"(a6), "+s"(a7),
+                     "+s"(b0), "+s"(b1), "+s"(b2), "+s"(b3), "+s"(b4), "+s"(b5), "+s"(b6), "+s"(b7));
+        const V4 all[16] = {a0, a1, a2, a3, a4, a5, a6, a7, b0, b1, b2, b3, b4, b5, b6, b7};
+        __builtin_memcpy(&r[0], all, sizeof(all));
+    } else {
+        asm volatile("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3), "+s"(a4), "+s"(a5), "+s"(a6), "+s"(a7));
+        const V4 all[8] = {a0, a1, a2, a3, a4, a5, a6, a7};
+        __builtin_memcpy(&r[0], all, sizeof(all));
+    }
+}
 
 // A lane's K samples tbase + lane + 64m: coordinates and |x|^2.  Samples at or
 // beyond S (padding) evaluate with x = 0 and are never returned.
@@ -35,6 +86,48 @@ struct LaneSamples {
     }
 };
 
+// The same samples rounded to binary32 (nearest even), for the binary32 factor.
+template <int K>
+struct LaneSamples32 {
+    float x0[K], x1[K], x2[K];
+    __device__ __forceinline__ void load(const double *__restrict__ x, int64_t S, int64_t xs, int64_t tbase,
+                                         int lane) {
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            const int64_t s = tbase + lane + kWave * m;
+            const bool in = s < S;
+            x0[m] = in ? static_cast<float>(x[s]) : 0.0f;
+            x1[m] = in ? static_cast<float>(x[xs + s]) : 0.0f;
+            x2[m] = in ? static_cast<float>(x[2 * xs + s]) : 0.0f;
+        }
+    }
+};
+
+template <int K>
+__device__ __forceinline__ double factor(const EdgeRec &e, const LaneSamples<K> &xs, int m) {
+    return edge_factor64(e, xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]);
+}
+template <int K>
+__device__ __forceinline__ float factor(const EdgeRec32 &e, const LaneSamples32<K> &xs, int m) {
+    return edge_factor32(e, xs.x0[m], xs.x1[m], xs.x2[m]);
+}
+
+// Record and sample types of the interior levels of a sweep with values of type T.
+template <typename T>
+struct SweepPath;
+template <>
+struct SweepPath<double> {
+    using Rec = EdgeRec;
+    template <int K>
+    using Samples = LaneSamples<K>;
+};
+template <>
+struct SweepPath<float> {
+    using Rec = EdgeRec32;
+    template <int K>
+    using Samples = LaneSamples32<K>;
+};
+
 // One wave computes destination rows [jbeg, jend) of a level for the tile at
 // tbase (64*K samples).  The rows' edges form one contiguous stream, walked in
 // chunks of four: the four records are fetched together (one scalar wait), the
@@ -49,10 +142,12 @@ struct LaneSamples {
 // Source rows are reached by 32-bit byte offsets (level buffers < 2 GiB).
 template <typename T, int K, bool FROM_ROOT, bool RESCALE>
 __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_ptr,
-                                                const EdgeRec *__restrict__ edges, int jbeg, int jend,
+                                                const typename SweepPath<T>::Rec *edges, int jbeg, int jend,
                                                 const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
-                                                int64_t tbase, int lane, const LaneSamples<K> &xs,
+                                                int64_t tbase, int lane,
+                                                const typename SweepPath<T>::template Samples<K> &xs,
                                                 const int (&esh)[K], uint32_t (&lmax)[K]) {
+    using Rec = typename SweepPath<T>::Rec;
     if (jbeg >= jend)
         return;
     T *const out_base = cur + tbase + lane;
@@ -68,45 +163,53 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
             crow[kWave * m] = z;
         }
     };
+    const ConstPtr<int32_t> rp = as_const(row_ptr);
     int j = jbeg;
-    int e = row_ptr[jbeg];
-    const int e_end = row_ptr[jend];
+    int e = rp[jbeg];
+    const int e_end = rp[jend];
     T acc[K];
 #pragma unroll
     for (int m = 0; m < K; ++m)
         acc[m] = T(0);
     // rows without in-edges at the start of the range
-    while (j < jend && row_ptr[j + 1] == e) {
+    while (j < jend && rp[j + 1] == e) {
         store_row(j, acc);
         ++j;
     }
-    const EdgeRec *rec = edges + e;
+    const Rec *rec = edges + e;
     const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
     const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(T));
     const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(T));
+    constexpr int C = kStreamChunk<Rec>;
     while (e < e_end) {
-        const int n = min(kChunk, e_end - e);
-        EdgeRec r[kChunk];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            r[u] = rec[u];  // past e_end: later edges or the zeroed pad, never used
-        // all 4*K source values are requested before any is used; records past
+        const int n = min(C, e_end - e);
+        Rec r[C];
+        load_chunk<C>(rec, r);  // past e_end: later edges or the zeroed pad, never used
+        // all C*K source values are requested before any is used; records past
         // the end name rows inside the level buffer (src < widest level), so
         // the unused reads stay in bounds
-        T v[kChunk][K];
+        T v[C][K];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
+        for (int u = 0; u < C; ++u) {
             const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
 #pragma unroll
             for (int m = 0; m < K; ++m)
                 v[u][m] = FROM_ROOT ? T(1) : *reinterpret_cast<const T *>(row + m * kWave * sizeof(T));
         }
+        // all C factors are formed unconditionally (a factor from a record past
+        // the stream is never added)
+        T w[C][K];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
+        for (int u = 0; u < C; ++u)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                w[u][m] = factor(r[u], xs, m);
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
             if (u < n) {
 #pragma unroll
                 for (int m = 0; m < K; ++m)
-                    acc[m] = fma_t(edge_factor<T>(r[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]), v[u][m], acc[m]);
+                    acc[m] = fma_t(w[u][m], v[u][m], acc[m]);
                 if (r[u].row_end) {
                     store_row(j, acc);
                     ++j;
@@ -161,9 +264,7 @@ __device__ __forceinline__ void final_quarter(const EdgeRec *__restrict__ edges,
     for (int e = e_lo; e < e_hi; e += kChunk) {
         const int n = min(kChunk, e_hi - e);
         EdgeRec r[kChunk];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            r[u] = edges[e + u];
+        load_chunk<kChunk>(edges + e, r);
         double v[kChunk][K];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
@@ -214,9 +315,7 @@ __device__ __forceinline__ void final_quarter_lds(const EdgeRec *__restrict__ ed
     for (int e = e_lo; e < e_hi; e += kChunk) {
         const int n = min(kChunk, e_hi - e);
         EdgeRec r[kChunk];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            r[u] = edges[e + u];
+        load_chunk<kChunk>(edges + e, r);
         double v[kChunk][K];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
@@ -239,7 +338,8 @@ constexpr int kFusedThreads = kFusedWaves * kWave;
 // Everything a workgroup needs to sweep one graph for one tile in LDS.
 struct FusedGraph {
     const int32_t *row_ptr;
-    const EdgeRec *edges;
+    const EdgeRec *edges;      // binary64 records (binary64 levels, final node)
+    const EdgeRec32 *edges32;  // binary32 records (binary32 levels)
     const LevelDev *levels;
     int32_t L;
     const double *x;
@@ -247,6 +347,62 @@ struct FusedGraph {
     double *out;
     int32_t *out_exp;
 };
+
+// One level of the whole-graph sweep for a wave's rows [jb, jb + nb): the
+// sums of each row (scaled by 2^-esh when RESCALE) into acc, the largest
+// |stored value| bit pattern into lmax.  rpl: lane i (i <= nb) holds the start
+// of row jb + i.  FROM_ROOT: level 1, whose only source is the root (value 1).
+template <typename T, int K, int RMAX, bool FROM_ROOT, bool RESCALE>
+__device__ __forceinline__ void fused_rows(const typename SweepPath<T>::Rec *edges, const T *vals, int nb, int rpl,
+                                           int lane, const typename SweepPath<T>::template Samples<K> &xs,
+                                           const int (&esh)[K], T (&acc)[RMAX][K], uint32_t (&lmax)[K]) {
+    using Rec = typename SweepPath<T>::Rec;
+    constexpr int kTile = kWave * K;
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        lmax[m] = 0u;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            acc[r][m] = T(0);
+        if (r < nb) {
+            const int e1 = __builtin_amdgcn_readlane(rpl, r + 1);
+            for (int e = __builtin_amdgcn_readlane(rpl, r); e < e1; e += kChunk) {
+                const int n = min(kChunk, e1 - e);
+                Rec rr[kChunk];
+                load_chunk<kChunk>(edges + e, rr);
+                // records past the row name rows < widest level: the unused
+                // LDS reads stay in bounds
+                T v[kChunk][K];
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        v[u][m] = FROM_ROOT ? T(1) : vals[rr[u].src * kTile + lane + kWave * m];
+                T w[kChunk][K];
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        w[u][m] = factor(rr[u], xs, m);
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u)
+                    if (u < n)
+#pragma unroll
+                        for (int m = 0; m < K; ++m)
+                            acc[r][m] = fma_t(w[u][m], v[u][m], acc[r][m]);
+            }
+            if constexpr (RESCALE) {
+#pragma unroll
+                for (int m = 0; m < K; ++m) {
+                    acc[r][m] = scale_pow2(acc[r][m], esh[m]);
+                    lmax[m] = max(lmax[m], abs_bits(acc[r][m]));
+                }
+            }
+        }
+    }
+}
 
 // Whole-graph sweep for the tile at tbase (64*K samples) by a group of 16
 // waves, the level held in LDS as [node][64K] (vals), wave w owning rows
@@ -257,8 +413,13 @@ template <typename T, int K, int RMAX, bool RESCALE>
 __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T *vals, uint32_t *red, double *part,
                                            int wave, int lane) {
     constexpr int kTile = kWave * K;
-    LaneSamples<K> xs;
+    typename SweepPath<T>::template Samples<K> xs;
     xs.load(G.x, G.S, G.S, tbase, lane);
+    const typename SweepPath<T>::Rec *edges;
+    if constexpr (sizeof(T) == sizeof(double))
+        edges = G.edges;
+    else
+        edges = G.edges32;
     int esh[K], E[K];  // e_{l-1} and the sum of e_1 .. e_{L-2} for this lane's samples
 #pragma unroll
     for (int m = 0; m < K; ++m) {
@@ -266,55 +427,18 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
         E[m] = 0;
     }
     for (int l = 1; l < G.L; ++l) {
-        const LevelDev lv = G.levels[l - 1];
-        const int32_t *rp = G.row_ptr + lv.rp_begin;
+        const LevelDev lv = load_level(G.levels, l - 1);
+        const ConstPtr<int32_t> rp = as_const(G.row_ptr) + lv.rp_begin;
         const int jb = min(wave * RMAX, lv.w_dst);
         const int nb = min(jb + RMAX, lv.w_dst) - jb;
         // lane i (i <= nb) holds the start of row jb + i: one load per wave and level
         const int rpl = lane <= nb ? rp[jb + lane] : 0;
         T acc[RMAX][K];
         uint32_t lmax[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m)
-            lmax[m] = 0u;
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                acc[r][m] = T(0);
-            if (r < nb) {
-                const int e1 = __builtin_amdgcn_readlane(rpl, r + 1);
-                for (int e = __builtin_amdgcn_readlane(rpl, r); e < e1; e += kChunk) {
-                    const int n = min(kChunk, e1 - e);
-                    EdgeRec rr[kChunk];
-#pragma unroll
-                    for (int u = 0; u < kChunk; ++u)
-                        rr[u] = G.edges[e + u];
-                    // records past the row name rows < widest level: the
-                    // unused LDS reads stay in bounds
-                    T v[kChunk][K];
-#pragma unroll
-                    for (int u = 0; u < kChunk; ++u)
-#pragma unroll
-                        for (int m = 0; m < K; ++m)
-                            v[u][m] = (l == 1) ? T(1) : vals[rr[u].src * kTile + lane + kWave * m];
-#pragma unroll
-                    for (int u = 0; u < kChunk; ++u)
-                        if (u < n)
-#pragma unroll
-                            for (int m = 0; m < K; ++m)
-                                acc[r][m] = fma_t(edge_factor<T>(rr[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]),
-                                                  v[u][m], acc[r][m]);
-                }
-                if constexpr (RESCALE) {
-#pragma unroll
-                    for (int m = 0; m < K; ++m) {
-                        acc[r][m] = scale_pow2(acc[r][m], esh[m]);
-                        lmax[m] = max(lmax[m], abs_bits(acc[r][m]));
-                    }
-                }
-            }
-        }
+        if (l == 1)
+            fused_rows<T, K, RMAX, true, RESCALE>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+        else
+            fused_rows<T, K, RMAX, false, RESCALE>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
         __syncthreads();  // every wave has finished reading level l-1
 #pragma unroll
         for (int r = 0; r < RMAX; ++r)
@@ -342,17 +466,23 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
         }
     }
 
-    // final node: quarter p holds edges [64p, 64p + 64) of the last level
-    const LevelDev lf = G.levels[G.L - 1];
+    // final node (binary64 factors from the binary64 records and samples):
+    // quarter p holds edges [64p, 64p + 64) of the last level
+    const LevelDev lf = load_level(G.levels, G.L - 1);
     const int nq = (lf.n_edges + kQuarter - 1) / kQuarter;
+    LaneSamples<K> xd;
+    if constexpr (sizeof(T) == sizeof(double))
+        xd = xs;
+    else if (wave < nq)
+        xd.load(G.x, G.S, G.S, tbase, lane);
     for (int p = wave; p < nq; p += kFusedWaves) {
         double acc[K];
         const int e_lo = p * kQuarter;
         const int e_hi = min(e_lo + kQuarter, lf.n_edges);
         if (G.L == 1)
-            final_quarter<T, K, true>(G.edges + lf.e_begin, e_lo, e_hi, nullptr, 0, 0, lane, xs, acc);
+            final_quarter<T, K, true>(G.edges + lf.e_begin, e_lo, e_hi, nullptr, 0, 0, lane, xd, acc);
         else
-            final_quarter_lds<T, K>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xs, acc);
+            final_quarter_lds<T, K>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xd, acc);
 #pragma unroll
         for (int m = 0; m < K; ++m)
             part[p * kTile + lane + kWave * m] = acc[m];
