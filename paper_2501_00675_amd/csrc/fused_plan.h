@@ -10,10 +10,15 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 constexpr int kMaxRows = 40;              // rows per wave supported (widest level 640)
 
 // Rows-per-wave variants; a (K, RMAX) pair is built only when its register
-// accumulators (K * RMAX values per lane) take at most 48 dwords, which keeps
-// every variant free of register spills at 1024 threads per group.
+// accumulators (K * RMAX values per lane) take at most 48 dwords and, with the
+// working set of one chunk of four edges (four source values and four factors
+// per sample), at most 80: this keeps every variant free of register spills at
+// 1024 threads per group (128 VGPRs).
 constexpr int kRowVariants[] = {2, 4, 8, 16, 24, kMaxRows};
-constexpr bool acc_fits(size_t elem, int K, int rmax) { return K * rmax * static_cast<int>(elem / 4) <= 48; }
+constexpr bool acc_fits(size_t elem, int K, int rmax) {
+    const int dw = static_cast<int>(elem / 4);
+    return K * rmax * dw <= 48 && K * rmax * dw + 8 * K * dw <= 80;
+}
 
 inline int rows_variant(int64_t rows) {
     for (int r : kRowVariants)

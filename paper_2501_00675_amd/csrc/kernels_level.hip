@@ -141,19 +141,34 @@ __global__ __launch_bounds__(kBlock) void fill_u32_kernel(uint32_t *__restrict__
 }
 
 constexpr int kRows = 8;      // consecutive rows per wave in the interior-level kernel
-constexpr int kK = 4;         // samples per lane (interior levels)
 constexpr int kKFinal = 2;    // samples per lane (final node)
-constexpr int64_t kL2Slice = 1 << 20;  // a tile slice up to this size is kept in one XCD's L2
+constexpr int64_t kL2Slice = int64_t(4) << 20;  // a tile slice up to this size is kept in one XCD's L2 (4 MB)
 constexpr bool kAlternateTiles = true;  // tile-major launches alternate their tile order level by level
 
-template <typename T, bool RESCALE>
-hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
+// Samples per lane of an interior level (tile = 64 K samples).  When the
+// tile's slice of the previous level fits in one XCD's L2, tiles are grouped
+// by XCD and the gathers hit L2: binary64 then takes K = 2 (half the registers
+// of K = 4, twice the waves per SIMD), binary32 the largest K in {4, 2} whose
+// slice fits.  Otherwise (wide levels) K = 4 amortises each record over the
+// most samples.  Measured on the mid and precision workloads.
+template <typename T>
+int level_k(int64_t w_src) {
+    const auto fits = [&](int K) { return w_src * kWave * K * static_cast<int64_t>(sizeof(T)) <= kL2Slice; };
+    if (sizeof(T) == sizeof(double))
+        return fits(2) ? 2 : 4;
+    if (fits(4))
+        return 4;
+    return fits(2) ? 2 : 4;
+}
+
+template <typename T, int K, bool RESCALE>
+hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
                           int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
     const LevelDesc &d = g.levels[l - 1];
     const int32_t rows_per_group = 4 * kRows;
     const int64_t n_rg = (d.w_dst + rows_per_group - 1) / rows_per_group;
-    const int64_t n_tiles = ld / (kWave * kK);
-    const int32_t xcd_group = d.w_src * kWave * kK * static_cast<int64_t>(sizeof(T)) <= kL2Slice ? 1 : 0;
+    const int64_t n_tiles = ld / (kWave * K);
+    const int32_t xcd_group = d.w_src * kWave * K * static_cast<int64_t>(sizeof(T)) <= kL2Slice ? 1 : 0;
     const int32_t reverse_tiles = kAlternateTiles && (l & 1) == 0 ? 1 : 0;
     const int64_t grid = (xcd_group ? round_up(n_tiles, kXcds) : n_tiles) * n_rg;
     if (grid <= 0)
@@ -168,16 +183,24 @@ hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, in
         recs = g.d_edges32;
     TimedLaunch tl(KK_LEVEL, s);
     if (prev == nullptr)
-        hipLaunchKernelGGL((level_gather_kernel<T, kK, kRows, true, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
+        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, true, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
                            recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
-                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, nullptr, static_cast<T *>(cur), ld, x, S, xs,
-                           prev_max, cur_max);
+                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, nullptr, static_cast<T *>(cur), ld,
+                           x, S, xs, prev_max, cur_max);
     else
-        hipLaunchKernelGGL((level_gather_kernel<T, kK, kRows, false, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
+        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, false, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
                            recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
                            static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, static_cast<const T *>(prev),
                            static_cast<T *>(cur), ld, x, S, xs, prev_max, cur_max);
     return hipGetLastError();
+}
+
+template <typename T, bool RESCALE>
+hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
+                          int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
+    if (level_k<T>(g.levels[l - 1].w_src) == 2)
+        return launch_level_k<T, 2, RESCALE>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
+    return launch_level_k<T, 4, RESCALE>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
 }
 
 }  // namespace

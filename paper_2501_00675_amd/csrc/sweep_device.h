@@ -5,6 +5,8 @@
 // node's edges in canonical order, with the same factor arithmetic.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels_common.h"
 
 namespace cosdag {
@@ -42,11 +44,13 @@ __device__ __forceinline__ LevelDev load_level(const LevelDev *levels, int i) {
 }
 
 // Fetch C consecutive records (C * sizeof(Rec) = 128 or 256 bytes) into scalar
-// registers at once.  The empty asm takes every 16-byte piece as an SGPR
-// operand, so all pieces are loaded (one scalar wait) before any field is
-// used; left alone, the compiler fetches each field next to its first use, one
-// dependent round trip per edge.
-template <int C, typename Rec>
+// registers.  TOGETHER: an empty asm takes every 16-byte piece as an SGPR
+// operand, so all pieces are loaded (one scalar wait) before any field is used
+// -- needed where fields are used under per-edge conditions or interleaved with
+// vector loads, where the compiler would otherwise fetch each field next to its
+// first use (one dependent round trip per edge).  Without it the compiler loads
+// only the fields used, which is enough where every use is unconditional.
+template <int C, bool TOGETHER, typename Rec>
 __device__ __forceinline__ void load_chunk(const Rec *p, Rec (&r)[C]) {
     static_assert(C <= kEdgePad, "a chunk starting at the last edge must stay inside the padded array");
     using V4 = __attribute__((ext_vector_type(4))) unsigned;
@@ -56,12 +60,14 @@ __device__ __forceinline__ void load_chunk(const Rec *p, Rec (&r)[C]) {
     V4 a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3], a4 = q[4], a5 = q[5], a6 = q[6], a7 = q[7];
     if constexpr (kBytes == 256) {
         V4 b0 = q[8], b1 = q[9], b2 = q[10], b3 = q[11], b4 = q[12], b5 = q[13], b6 = q[14], b7 = q[15];
-        asm volatile("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3), "+s"(a4), "+s"(a5), "+s"(a6), "+s"(a7),
-                     "+s"(b0), "+s"(b1), "+s"(b2), "+s"(b3), "+s"(b4), "+s"(b5), "+s"(b6), "+s"(b7));
+        if constexpr (TOGETHER)
+            asm volatile("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3), "+s"(a4), "+s"(a5), "+s"(a6), "+s"(a7),
+                         "+s"(b0), "+s"(b1), "+s"(b2), "+s"(b3), "+s"(b4), "+s"(b5), "+s"(b6), "+s"(b7));
         const V4 all[16] = {a0, a1, a2, a3, a4, a5, a6, a7, b0, b1, b2, b3, b4, b5, b6, b7};
         __builtin_memcpy(&r[0], all, sizeof(all));
     } else {
-        asm volatile("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3), "+s"(a4), "+s"(a5), "+s"(a6), "+s"(a7));
+        if constexpr (TOGETHER)
+            asm volatile("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3), "+s"(a4), "+s"(a5), "+s"(a6), "+s"(a7));
         const V4 all[8] = {a0, a1, a2, a3, a4, a5, a6, a7};
         __builtin_memcpy(&r[0], all, sizeof(all));
     }
@@ -181,10 +187,12 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
     const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(T));
     const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(T));
     constexpr int C = kStreamChunk<Rec>;
-    while (e < e_end) {
-        const int n = min(C, e_end - e);
+    // one chunk of the stream: records, source values and factors, then the
+    // accumulation edge by edge (every edge of a full chunk, the first n of the
+    // tail), storing each row at its flagged last edge
+    auto chunk = [&](auto full, int n) {
         Rec r[C];
-        load_chunk<C>(rec, r);  // past e_end: later edges or the zeroed pad, never used
+        load_chunk<C, true>(rec, r);  // past e_end: later edges or the zeroed pad, never used
         // all C*K source values are requested before any is used; records past
         // the end name rows inside the level buffer (src < widest level), so
         // the unused reads stay in bounds
@@ -196,8 +204,6 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
             for (int m = 0; m < K; ++m)
                 v[u][m] = FROM_ROOT ? T(1) : *reinterpret_cast<const T *>(row + m * kWave * sizeof(T));
         }
-        // all C factors are formed unconditionally (a factor from a record past
-        // the stream is never added)
         T w[C][K];
 #pragma unroll
         for (int u = 0; u < C; ++u)
@@ -206,7 +212,7 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
                 w[u][m] = factor(r[u], xs, m);
 #pragma unroll
         for (int u = 0; u < C; ++u) {
-            if (u < n) {
+            if (decltype(full)::value || u < n) {
 #pragma unroll
                 for (int m = 0; m < K; ++m)
                     acc[m] = fma_t(w[u][m], v[u][m], acc[m]);
@@ -223,9 +229,11 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
                 }
             }
         }
-        rec += n;
-        e += n;
-    }
+    };
+    for (; e + C <= e_end; e += C, rec += C)
+        chunk(std::true_type{}, C);
+    if (e < e_end)
+        chunk(std::false_type{}, e_end - e);
 }
 
 // Largest |value| bit patterns of NW waves (lmax of each lane) combined in LDS
@@ -250,36 +258,61 @@ __device__ __forceinline__ void fold_max(uint32_t *red /* LDS [NW][64K] */, cons
 }
 
 // Sum over final-node edges [e_lo, e_hi) of w_e(x) v_{L-1}[src_e] in binary64,
-// sequentially in canonical order (one quarter of a final-node chunk).
+// sequentially in canonical order (one quarter of a final-node chunk).  The
+// source value of edge e comes from src_value(rec, m) (level buffer or LDS).
+// Full chunks accumulate unconditionally, a tail its first n edges only.
+template <int K, bool TOGETHER, typename SrcValue>
+__device__ __forceinline__ void final_sum(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
+                                          const LaneSamples<K> &xs, SrcValue src_value, double (&acc)[K]) {
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        acc[m] = 0.0;
+    auto chunk = [&](auto full, int e, int n) {
+        EdgeRec r[kChunk];
+        load_chunk<kChunk, TOGETHER>(edges + e, r);
+        double v[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                v[u][m] = src_value(r[u], m);
+        double w[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                w[u][m] = factor(r[u], xs, m);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            if (decltype(full)::value || u < n)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    acc[m] = __builtin_fma(w[u][m], v[u][m], acc[m]);
+    };
+    int e = e_lo;
+    for (; e + kChunk <= e_hi; e += kChunk)
+        chunk(std::true_type{}, e, kChunk);
+    if (e < e_hi)
+        chunk(std::false_type{}, e, e_hi - e);
+}
+
+// final_sum with the level L-1 values in a level buffer (streamed kernels; the
+// records are fetched together, ahead of the vector loads).
 template <typename TV, int K, bool FROM_ROOT>
 __device__ __forceinline__ void final_quarter(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
                                               const TV *__restrict__ prev, int64_t ld, int64_t tbase, int lane,
                                               const LaneSamples<K> &xs, double (&acc)[K]) {
-#pragma unroll
-    for (int m = 0; m < K; ++m)
-        acc[m] = 0.0;
     const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
     const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(TV));
     const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(TV));
-    for (int e = e_lo; e < e_hi; e += kChunk) {
-        const int n = min(kChunk, e_hi - e);
-        EdgeRec r[kChunk];
-        load_chunk<kChunk>(edges + e, r);
-        double v[kChunk][K];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                v[u][m] = FROM_ROOT ? 1.0 : static_cast<double>(*reinterpret_cast<const TV *>(row + m * kWave * sizeof(TV)));
+    final_sum<K, true>(edges, e_lo, e_hi, xs, [&](const EdgeRec &r, int m) -> double {
+        if constexpr (FROM_ROOT) {
+            return 1.0;
+        } else {
+            const char *row = src_tile + static_cast<uint32_t>(r.src) * row_bytes + lane_off;
+            return static_cast<double>(*reinterpret_cast<const TV *>(row + m * kWave * sizeof(TV)));
         }
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            if (u < n)
-#pragma unroll
-                for (int m = 0; m < K; ++m)
-                    acc[m] = __builtin_fma(edge_factor64(r[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]), v[u][m], acc[m]);
-    }
+    }, acc);
 }
 
 // Final node, second pass for sample s: the chunk partial sums added in
@@ -303,32 +336,19 @@ __device__ __forceinline__ void final_combine_one(const double *__restrict__ par
     }
 }
 
-// final_quarter with the level L-1 values read from LDS ([node][64K]).
-template <typename T, int K>
+// final_sum with the level L-1 values read from LDS ([node][64K]) or, for
+// L = 1, the root's value 1.
+template <typename T, int K, bool FROM_ROOT>
 __device__ __forceinline__ void final_quarter_lds(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
                                                   const T *vals, int lane, const LaneSamples<K> &xs,
                                                   double (&acc)[K]) {
     constexpr int kTile = kWave * K;
-#pragma unroll
-    for (int m = 0; m < K; ++m)
-        acc[m] = 0.0;
-    for (int e = e_lo; e < e_hi; e += kChunk) {
-        const int n = min(kChunk, e_hi - e);
-        EdgeRec r[kChunk];
-        load_chunk<kChunk>(edges + e, r);
-        double v[kChunk][K];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                v[u][m] = static_cast<double>(vals[r[u].src * kTile + lane + kWave * m]);
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            if (u < n)
-#pragma unroll
-                for (int m = 0; m < K; ++m)
-                    acc[m] = __builtin_fma(edge_factor64(r[u], xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]), v[u][m], acc[m]);
-    }
+    final_sum<K, false>(edges, e_lo, e_hi, xs, [&](const EdgeRec &r, int m) -> double {
+        if constexpr (FROM_ROOT)
+            return 1.0;
+        else
+            return static_cast<double>(vals[r.src * kTile + lane + kWave * m]);
+    }, acc);
 }
 
 // ---------------------------------------------------------------- fused sweep
@@ -368,10 +388,11 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T>::Rec *edg
             acc[r][m] = T(0);
         if (r < nb) {
             const int e1 = __builtin_amdgcn_readlane(rpl, r + 1);
-            for (int e = __builtin_amdgcn_readlane(rpl, r); e < e1; e += kChunk) {
-                const int n = min(kChunk, e1 - e);
+            // one chunk of the row: its records, source values and factors, then
+            // the accumulation (every edge of a full chunk, the first n of a tail)
+            auto chunk = [&](auto full, int e, int n) {
                 Rec rr[kChunk];
-                load_chunk<kChunk>(edges + e, rr);
+                load_chunk<kChunk, false>(edges + e, rr);
                 // records past the row name rows < widest level: the unused
                 // LDS reads stay in bounds
                 T v[kChunk][K];
@@ -388,11 +409,16 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T>::Rec *edg
                         w[u][m] = factor(rr[u], xs, m);
 #pragma unroll
                 for (int u = 0; u < kChunk; ++u)
-                    if (u < n)
+                    if (decltype(full)::value || u < n)
 #pragma unroll
                         for (int m = 0; m < K; ++m)
                             acc[r][m] = fma_t(w[u][m], v[u][m], acc[r][m]);
-            }
+            };
+            int e = __builtin_amdgcn_readlane(rpl, r);
+            for (; e + kChunk <= e1; e += kChunk)
+                chunk(std::true_type{}, e, kChunk);
+            if (e < e1)
+                chunk(std::false_type{}, e, e1 - e);
             if constexpr (RESCALE) {
 #pragma unroll
                 for (int m = 0; m < K; ++m) {
@@ -480,9 +506,9 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
         const int e_lo = p * kQuarter;
         const int e_hi = min(e_lo + kQuarter, lf.n_edges);
         if (G.L == 1)
-            final_quarter<T, K, true>(G.edges + lf.e_begin, e_lo, e_hi, nullptr, 0, 0, lane, xd, acc);
+            final_quarter_lds<T, K, true>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xd, acc);
         else
-            final_quarter_lds<T, K>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xd, acc);
+            final_quarter_lds<T, K, false>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xd, acc);
 #pragma unroll
         for (int m = 0; m < K; ++m)
             part[p * kTile + lane + kWave * m] = acc[m];
