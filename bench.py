@@ -84,15 +84,21 @@ def cpu_baseline_leg(g, x, idx_ref, target_s: float = 12.0):
     dt = max(time.perf_counter() - t0, 1e-6)
     n = int(min(S, max(cal, cal * target_s / dt)))
     xs = np.ascontiguousarray(x[:, :n])
+    # a workload the oracle finishes quickly is swept repeatedly until about target_s seconds have run
+    reps = 0
     t0 = time.perf_counter()
-    _, used = oracle.sweep(g, xs, return_threads=True)
-    t = time.perf_counter() - t0
+    while True:
+        _, used = oracle.sweep(g, xs, return_threads=True)
+        reps += 1
+        t = time.perf_counter() - t0
+        if t >= 0.9 * target_s or reps >= 10000:
+            break
     xr = np.ascontiguousarray(x[:, idx_ref])
     V = oracle.sweep(g, xr, "value")
     Q = oracle.sweep(g, xr, "square")
-    base = {"value": E * n / t, "unit": UNIT, "cores": int(used), "kind": "oracle",
+    base = {"value": E * n * reps / t, "unit": UNIT, "cores": int(used), "kind": "oracle",
             "sample": f"first {n} of {S} samples of the same graph ({E} edges), FP64 level sweep, "
-                      f"{t:.1f} s on {cpu_info()}"}
+                      f"{reps} pass(es), {t:.1f} s on {cpu_info()}"}
     return base, V, Q
 
 
