@@ -38,6 +38,8 @@ def build(out: str = _LIB, src: str = _SRC, defines: tuple = ()) -> str:
            "-fno-fast-math", f'-DORACLE_SRC_HASH="{_src_hash(src)}"', *defines,
            "-o", out, src, "-lm"]
     subprocess.run(cmd, check=True)
+    with open(out + ".srchash", "w") as f:
+        f.write(_src_hash(src))
     return out
 
 
@@ -48,6 +50,10 @@ def _bind(lib):
     lib.oracle_check.argtypes = [i32, p, p, p, p, p, p, p]
     lib.oracle_sweep.restype = ctypes.c_int
     lib.oracle_sweep.argtypes = [i32, p, p, p, p, p, p, p, p, i64, i32, i32, p, p]
+    lib.oracle_check_lookup.restype = ctypes.c_int
+    lib.oracle_check_lookup.argtypes = [i32, p, p, p, p, p, p, i32]
+    lib.oracle_sweep_lookup.restype = ctypes.c_int
+    lib.oracle_sweep_lookup.argtypes = [i32, p, p, p, p, p, p, i32, p, i64, i32, i32, p, p]
     return lib
 
 
@@ -60,11 +66,20 @@ def load(path: str = _LIB, rebuild_if_stale: bool = True):
         if not rebuild_if_stale:
             raise FileNotFoundError(path)
         build(path)
+    if path == _LIB and rebuild_if_stale:
+        # decided from the hash file written beside the library, before any dlopen
+        # (a library once loaded stays mapped under its path for the process)
+        try:
+            with open(path + ".srchash") as f:
+                stale = f.read().strip() != _src_hash()
+        except OSError:
+            stale = True
+        if stale:
+            build(path)
     lib = _bind(ctypes.CDLL(path))
     if path == _LIB:
-        if lib.oracle_src_hash().decode() != _src_hash() and rebuild_if_stale:
-            build(path)
-            lib = _bind(ctypes.CDLL(path))
+        if lib.oracle_src_hash().decode() != _src_hash():
+            raise ImportError(f"{path} was built from other sources; rebuild with oracle.build()")
         _lib = lib
     return lib
 
@@ -73,38 +88,60 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _is_lookup(g) -> bool:
+    return getattr(g, "slot", None) is not None
+
+
 def _arrays(g):
-    return dict(
+    A = dict(
         widths=np.ascontiguousarray(g.widths, dtype=np.int64),
         epl=np.ascontiguousarray(g.epl, dtype=np.int64),
         src=np.ascontiguousarray(g.src, dtype=np.int32),
         dst=np.ascontiguousarray(g.dst, dtype=np.int32),
-        a=np.ascontiguousarray(g.a, dtype=np.float64),
-        b=np.ascontiguousarray(g.b, dtype=np.float64),
-        k=np.ascontiguousarray(g.k, dtype=np.float64).reshape(-1),
     )
+    if _is_lookup(g):
+        A.update(slot=np.ascontiguousarray(g.slot, dtype=np.int32),
+                 coef=np.ascontiguousarray(g.coef, dtype=np.float64))
+    else:
+        A.update(a=np.ascontiguousarray(g.a, dtype=np.float64),
+                 b=np.ascontiguousarray(g.b, dtype=np.float64),
+                 k=np.ascontiguousarray(g.k, dtype=np.float64).reshape(-1))
+    return A
 
 
 def check(g, lib=None) -> bool:
     lib = lib or load()
     A = _arrays(g)
+    if _is_lookup(g):
+        return lib.oracle_check_lookup(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "slot", "coef")],
+                                       int(g.n_slots)) == 0
     return lib.oracle_check(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "a", "b", "k")]) == 0
 
 
 def sweep(g, x, mode: str = "value", threads: int = 0, lib=None, return_threads: bool = False):
-    """Evaluate the final-node value (or its |w| / w^2 norm sweeps) for x[3,S]."""
+    """Evaluate the final-node value (or its |w| / w^2 norm sweeps).
+
+    x: float64[3, S] sample coordinates for a graph with rational factors, or
+    float64[n_slots, S] per-sample tables for a graph with lookup factors.
+    """
     lib = lib or load()
     A = _arrays(g)
     x = np.ascontiguousarray(x, dtype=np.float64)
-    if x.ndim != 2 or x.shape[0] != 3:
-        raise ValueError("x must be float64[3, S]")
+    rows = int(g.n_slots) if _is_lookup(g) else 3
+    if x.ndim != 2 or x.shape[0] != rows:
+        raise ValueError(f"x must be float64[{rows}, S]")
     S = x.shape[1]
     out = np.empty(S, dtype=np.float64)
     used = ctypes.c_int32(0)
-    rc = lib.oracle_sweep(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "a", "b", "k")],
-                          _ptr(x), S, MODES[mode], int(threads), _ptr(out), ctypes.byref(used))
+    if _is_lookup(g):
+        rc = lib.oracle_sweep_lookup(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "slot", "coef")],
+                                     int(g.n_slots), _ptr(x), S, MODES[mode], int(threads), _ptr(out),
+                                     ctypes.byref(used))
+    else:
+        rc = lib.oracle_sweep(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "a", "b", "k")],
+                              _ptr(x), S, MODES[mode], int(threads), _ptr(out), ctypes.byref(used))
     if rc != 0:
-        raise ValueError(f"oracle_sweep failed with code {rc}")
+        raise ValueError(f"oracle sweep failed with code {rc}")
     return (out, used.value) if return_threads else out
 
 

@@ -14,8 +14,12 @@
  * are evaluated one after another, each level fully before the next (Sec. II.C,
  * "Windowing": a parent node is complete before its out-edges are applied).
  *
- * Edge factor (the synthetic stand-in for a Green's function):
- *     w_e(x) = a_e / (1 + b_e * |x - k_e|^2),  x, k_e in R^3.
+ * Edge factors, two kinds:
+ *   rational (the synthetic stand-in for a Green's function of the sample's
+ *   coordinates):   w_e(x) = a_e / (1 + b_e * |x - k_e|^2),  x, k_e in R^3;
+ *   lookup (the paper's own form, Sec. II.B and Sec. III: a Green's function
+ *   G_ab between two of the sample's vertices, times a fermion-loop sign or
+ *   other constant):  w_e(s) = c_e * T_s[slot_e], T_s the sample's table.
  *
  * Arithmetic: IEEE binary64, no FMA contraction (build with -ffp-contract=off),
  * edges summed in the order the caller supplies them.  Samples are independent;
@@ -87,6 +91,42 @@ int oracle_check(int32_t L, const int64_t *widths, const int64_t *epl,
     return ORACLE_OK;
 }
 
+/* Validation of a lookup graph: the same structure rules, slots inside the
+   table, finite constants. */
+int oracle_check_lookup(int32_t L, const int64_t *widths, const int64_t *epl,
+                        const int32_t *src, const int32_t *dst, const int32_t *slot,
+                        const double *coef, int32_t n_slots)
+{
+    if (L < 1 || widths[0] != 1 || widths[L] != 1 || n_slots < 1)
+        return ORACLE_EINVAL;
+    int64_t n_nodes = 0;
+    for (int32_t l = 0; l <= L; ++l) {
+        if (widths[l] < 1)
+            return ORACLE_EINVAL;
+        n_nodes += widths[l];
+    }
+    if (n_nodes > INT32_MAX)
+        return ORACLE_EINVAL;
+    int64_t first = 0;
+    int64_t e = 0;
+    for (int32_t l = 1; l <= L; ++l) {
+        int64_t lo_src = first, hi_src = first + widths[l - 1];
+        int64_t lo_dst = hi_src, hi_dst = hi_src + widths[l];
+        if (epl[l - 1] < 0)
+            return ORACLE_EINVAL;
+        for (int64_t i = 0; i < epl[l - 1]; ++i, ++e) {
+            if (src[e] < lo_src || src[e] >= hi_src)
+                return ORACLE_EINVAL;
+            if (dst[e] < lo_dst || dst[e] >= hi_dst)
+                return ORACLE_EINVAL;
+            if (slot[e] < 0 || slot[e] >= n_slots || !isfinite(coef[e]))
+                return ORACLE_EINVAL;
+        }
+        first = hi_src;
+    }
+    return ORACLE_OK;
+}
+
 /* The edge factor, literally as defined. */
 static double edge_factor(double a, double b, const double *k, double x0, double x1, double x2)
 {
@@ -98,18 +138,15 @@ static double edge_factor(double a, double b, const double *k, double x0, double
 }
 
 /*
- * x: float64[3][S] (structure of arrays), out: float64[S].
- * nthreads <= 0 leaves the OpenMP default.  *threads_used (nullable) receives
- * the number of threads that ran.
+ * The sweep for either kind.  kind 0: x is float64[3][S] (coordinates), the
+ * factor rational; kind 1: x is float64[n_slots][S] (each sample's table
+ * T_s[slot] = x[slot * S + s]), the factor c_e * T_s[slot_e].  out: float64[S].
  */
-int oracle_sweep(int32_t L, const int64_t *widths, const int64_t *epl,
-                 const int32_t *src, const int32_t *dst, const double *a,
-                 const double *b, const double *k, const double *x, int64_t S,
-                 int32_t mode, int32_t nthreads, double *out, int32_t *threads_used)
+static int sweep(int32_t kind, int32_t L, const int64_t *widths, const int64_t *epl,
+                 const int32_t *src, const int32_t *dst, const double *a, const double *b,
+                 const double *k, const int32_t *slot, const double *coef, const double *x,
+                 int64_t S, int32_t mode, int32_t nthreads, double *out, int32_t *threads_used)
 {
-    int rc = oracle_check(L, widths, epl, src, dst, a, b, k);
-    if (rc != ORACLE_OK)
-        return rc;
     if (S < 0 || mode < 0 || mode > 2)
         return ORACLE_EINVAL;
     int64_t n_nodes = 0;
@@ -173,7 +210,11 @@ int oracle_sweep(int32_t L, const int64_t *widths, const int64_t *epl,
                 for (int64_t e = edge_first[l - 1]; e < edge_first[l]; ++e) {
                     for (int64_t j = 0; j < nb; ++j) {
                         int64_t s = s0 + j;
-                        double w = edge_factor(a[e], b[e], &k[3 * e], x[s], x[S + s], x[2 * S + s]);
+                        double w;
+                        if (kind == 0)
+                            w = edge_factor(a[e], b[e], &k[3 * e], x[s], x[S + s], x[2 * S + s]);
+                        else
+                            w = coef[e] * x[(int64_t)slot[e] * S + s];
                         if (mode == 1)
                             w = fabs(w);
                         else if (mode == 2)
@@ -192,4 +233,33 @@ int oracle_sweep(int32_t L, const int64_t *widths, const int64_t *epl,
     if (threads_used)
         *threads_used = used;
     return failed ? ORACLE_ENOMEM : ORACLE_OK;
+}
+
+/*
+ * Rational factors.  x: float64[3][S] (structure of arrays), out: float64[S].
+ * nthreads <= 0 leaves the OpenMP default.  *threads_used (nullable) receives
+ * the number of threads that ran.
+ */
+int oracle_sweep(int32_t L, const int64_t *widths, const int64_t *epl,
+                 const int32_t *src, const int32_t *dst, const double *a,
+                 const double *b, const double *k, const double *x, int64_t S,
+                 int32_t mode, int32_t nthreads, double *out, int32_t *threads_used)
+{
+    int rc = oracle_check(L, widths, epl, src, dst, a, b, k);
+    if (rc != ORACLE_OK)
+        return rc;
+    return sweep(0, L, widths, epl, src, dst, a, b, k, NULL, NULL, x, S, mode, nthreads, out, threads_used);
+}
+
+/* Lookup factors.  table: float64[n_slots][S], out: float64[S]. */
+int oracle_sweep_lookup(int32_t L, const int64_t *widths, const int64_t *epl,
+                        const int32_t *src, const int32_t *dst, const int32_t *slot,
+                        const double *coef, int32_t n_slots, const double *table, int64_t S,
+                        int32_t mode, int32_t nthreads, double *out, int32_t *threads_used)
+{
+    int rc = oracle_check_lookup(L, widths, epl, src, dst, slot, coef, n_slots);
+    if (rc != ORACLE_OK)
+        return rc;
+    return sweep(1, L, widths, epl, src, dst, NULL, NULL, NULL, slot, coef, table, S, mode, nthreads, out,
+                 threads_used);
 }

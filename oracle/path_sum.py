@@ -22,6 +22,11 @@ def edge_factor_exact(a, b, k, x) -> Fraction:
     return Fraction(float(a)) / (1 + Fraction(float(b)) * r2)
 
 
+def lookup_factor_exact(coef, slot, table_col) -> Fraction:
+    """w = c * T[slot] (the sample's table entry for the edge's vertex pair) in exact rationals."""
+    return Fraction(float(coef)) * Fraction(float(table_col[int(slot)]))
+
+
 def enumerate_paths(g):
     """All root-to-final paths as lists of edge indices (depth-first)."""
     out_edges = {}
@@ -41,12 +46,17 @@ def enumerate_paths(g):
 
 
 def path_sum(g, x_col, weight=None):
-    """Exact V(x) = sum over paths of prod_e w_e(x) for one sample x = (x0,x1,x2).
+    """Exact V = sum over paths of prod_e w_e for one sample: x_col = (x0, x1, x2)
+    for rational factors, or the sample's table column (n_slots values) for
+    lookup factors.
 
     weight: optional function Fraction -> Fraction applied to each factor
     (abs for the 1-norm, square for the squared 2-norm).
     """
-    w = [edge_factor_exact(g.a[e], g.b[e], g.k[e], x_col) for e in range(g.n_edges)]
+    if getattr(g, "slot", None) is not None:
+        w = [lookup_factor_exact(g.coef[e], g.slot[e], x_col) for e in range(g.n_edges)]
+    else:
+        w = [edge_factor_exact(g.a[e], g.b[e], g.k[e], x_col) for e in range(g.n_edges)]
     if weight is not None:
         w = [weight(v) for v in w]
     total = Fraction(0)

@@ -9,7 +9,11 @@ the oracle disagrees with:
   * the closed form of level-constant factors on in-regular graphs,
   * exact path counts Prod_l d_l of in-regular graphs with unit factors,
   * transpose invariance V(G) = V(G^T),
-  * exact power-of-two scaling and negation of one level.
+  * exact power-of-two scaling and negation of one level;
+
+and the same facts for lookup factors w_e = c_e T[slot_e] (the paper's Green's
+function per vertex pair times a fermion-loop sign), plus exact invariance
+under a relabelling of the table entries.
 
 Error bounds use the standard model fl(a op b) = (a op b)(1 + d), |d| <= u:
 the factor takes <= 8 roundings and a level adds one product and at most d_l
@@ -211,5 +215,101 @@ def pin_pow2_scaling(lib, seed=41):
         assert np.array_equal(vs, v * f), (l, f)
 
 
+# ---------------------------------------------------------------- lookup factors
+# w_e = c_e * T[slot_e]: one rounding per factor, so the rational bound
+# gamma_K (K = sum_l (9 + d_l)) holds with room to spare.
+
+
+def dyadic_lookup(g, rng, n_slots):
+    """Lookup factors with dyadic constants (signs and halves) on g's structure."""
+    E = g.n_edges
+    coef = dyadic(rng, E, -1, 1, bits=1)
+    coef[coef == 0] = 1.0
+    return g.with_lookup(rng.integers(0, n_slots, E), coef, n_slots)
+
+
+def pin_lookup_exact_path_sum(lib, n_random=10, n_samples=3, seed=51):
+    rng = np.random.default_rng(seed)
+    fig, _ = load_figure_graph()
+    tiny, _ = make_config("tiny", S=4)
+    graphs = [dyadic_lookup(fig, rng, 5), dyadic_lookup(tiny, rng, 4)]
+    graphs += [dyadic_lookup(random_small_graph(rng), rng, int(rng.integers(1, 9))) for _ in range(n_random)]
+    for g in graphs:
+        T = dyadic(rng, (g.n_slots, n_samples), -1, 1)
+        V = oracle.sweep(g, T, "value", lib=lib)
+        A = oracle.sweep(g, T, "abs", lib=lib)
+        Q = oracle.sweep(g, T, "square", lib=lib)
+        tol = gamma(error_K(g))
+        for j in range(n_samples):
+            ex_v = path_sum(g, T[:, j])
+            ex_a = path_sum(g, T[:, j], weight=abs)
+            ex_q = path_sum(g, T[:, j], weight=lambda w: w * w)
+            bound = Fraction(tol) * ex_a
+            assert abs(Fraction(float(V[j])) - ex_v) <= bound, (g.widths, j, V[j], float(ex_v))
+            assert abs(Fraction(float(A[j])) - ex_a) <= bound, (g.widths, j, A[j], float(ex_a))
+            assert abs(Fraction(float(Q[j])) - ex_q) <= Fraction(tol) * ex_q, (g.widths, j, Q[j], float(ex_q))
+
+
+def pin_lookup_level_constant(lib, seed=61):
+    """Every edge of level l reads slot s_l with constant c_l: V = prod_l d_l c_l T[s_l]."""
+    rng = np.random.default_rng(seed)
+    for name, S in (("tiny", 64), ("mid", 64), ("precision", 8)):
+        g, _ = make_config(name, S=S)
+        d = in_degrees(g)
+        n_slots = 7
+        sl = rng.integers(0, n_slots, g.L)
+        cl = rng.uniform(-2, 2, g.L)
+        lev = np.repeat(np.arange(g.L), g.epl)
+        gl = g.with_lookup(sl[lev], cl[lev], n_slots)
+        T = rng.uniform(-1, 1, (n_slots, S))
+        v = oracle.sweep(gl, T, lib=lib)
+        cf = np.ones(S)
+        for l in range(g.L):
+            cf = cf * (d[l] * cl[l] * T[sl[l]])
+        tol = gamma(error_K(g)) + gamma(2 * g.L)
+        rel = np.abs(v - cf) / np.abs(cf)
+        assert rel.max() <= tol, (name, rel.max(), tol)
+
+
+def pin_lookup_all_ones(lib):
+    expect = {"tiny": 12, "mid": 4 ** 10 * 256, "precision": 8 ** 22 * 4096}
+    for name, count in expect.items():
+        g, _ = make_config(name, S=2)
+        g1 = g.with_lookup(0, 1.0, 3)
+        T = np.array([[1.0, 1.0], [5.0, -3.0], [0.0, 7.0]])  # only slot 0 is read
+        v = oracle.sweep(g1, T, lib=lib)
+        assert np.all(v == float(count)), (name, v, count)
+
+
+def pin_lookup_sign_and_scale(lib, seed=71):
+    """Negating or scaling by 2^k the constants of one level does the same to V, exactly;
+    permuting the table rows along with the slots leaves V unchanged, exactly."""
+    g, _ = make_config("mid", S=16, seed=seed, factor="lookup")
+    rng = np.random.default_rng(seed)
+    T = rng.uniform(-1, 1, (g.n_slots, 16))
+    v = oracle.sweep(g, T, lib=lib)
+    lev = np.repeat(np.arange(g.L), g.epl)
+    for l, f in ((2, -1.0), (g.L - 1, 4.0), (0, 0.5)):
+        c = g.coef.copy()
+        c[lev == l] *= f
+        vs = oracle.sweep(g.with_lookup(g.slot, c, g.n_slots), T, lib=lib)
+        assert np.array_equal(vs, v * f), (l, f)
+    perm = rng.permutation(g.n_slots)
+    inv = np.argsort(perm)
+    vp = oracle.sweep(g.with_lookup(inv[g.slot], g.coef, g.n_slots), T[perm], lib=lib)
+    assert np.array_equal(vp, v)
+
+
+def pin_lookup_transpose(lib, seed=81):
+    for name, S in (("tiny", 32), ("mid", 32)):
+        g, T = make_config(name, S=S, seed=seed, factor="lookup")
+        gt = transpose(g)
+        v, q = oracle.sweep(g, T, lib=lib), oracle.sweep(g, T, "square", lib=lib)
+        vt = oracle.sweep(gt, T, lib=lib)
+        err = oracle.scaled_error(vt, v, q)
+        assert err.max() <= 1e-13, (name, err.max())
+
+
 ALL_PINS = [pin_paper_figure, pin_exact_path_sum, pin_level_constant_closed_form,
-            pin_all_ones_counts, pin_transpose, pin_pow2_scaling]
+            pin_all_ones_counts, pin_transpose, pin_pow2_scaling, pin_lookup_exact_path_sum,
+            pin_lookup_level_constant, pin_lookup_all_ones, pin_lookup_sign_and_scale, pin_lookup_transpose]

@@ -38,6 +38,36 @@ def test_pow2_scaling_exact(oracle_lib):
     pins.pin_pow2_scaling(oracle_lib)
 
 
+def test_lookup_exact_path_sum(oracle_lib):
+    pins.pin_lookup_exact_path_sum(oracle_lib)
+
+
+def test_lookup_level_constant_closed_form(oracle_lib):
+    pins.pin_lookup_level_constant(oracle_lib)
+
+
+def test_lookup_all_ones_path_counts(oracle_lib):
+    pins.pin_lookup_all_ones(oracle_lib)
+
+
+def test_lookup_sign_scale_and_relabel_exact(oracle_lib):
+    pins.pin_lookup_sign_and_scale(oracle_lib)
+
+
+def test_lookup_transpose_invariance(oracle_lib):
+    pins.pin_lookup_transpose(oracle_lib)
+
+
+def test_lookup_rejects_bad_slots(oracle_lib):
+    g, T = make_config("tiny", S=4, factor="lookup")
+    bad = g.with_lookup(g.slot, g.coef, g.n_slots)
+    bad.slot[3] = g.n_slots  # outside the table
+    with pytest.raises(ValueError):
+        oracle.sweep(bad, T, lib=oracle_lib)
+    with pytest.raises(ValueError):  # the table must have n_slots rows
+        oracle.sweep(g, T[:-1], lib=oracle_lib)
+
+
 def test_thread_count_does_not_change_bits(oracle_lib):
     g, x = make_config("mid", S=100)
     v1 = oracle.sweep(g, x, threads=1, lib=oracle_lib)

@@ -24,6 +24,14 @@ MUTANTS = {
     "r_not_squared": ("return a / (1.0 + b * r2);", "return a / (1.0 + b * sqrt(r2));"),
     "root_not_one": ("value[0 * SAMPLE_BLOCK + j] = 1.0;", "value[0 * SAMPLE_BLOCK + j] = 2.0;"),
     "level_not_cleared": ("value[n * SAMPLE_BLOCK + j] = 0.0;", "value[n * SAMPLE_BLOCK + j] = 1.0;"),
+    # lookup factors
+    "lookup_constant_dropped": ("w = coef[e] * x[(int64_t)slot[e] * S + s];", "w = x[(int64_t)slot[e] * S + s];"),
+    "lookup_wrong_slot": ("w = coef[e] * x[(int64_t)slot[e] * S + s];",
+                          "w = coef[e] * x[(int64_t)(slot[e] > 0 ? slot[e] - 1 : 0) * S + s];"),
+    "lookup_wrong_sample": ("w = coef[e] * x[(int64_t)slot[e] * S + s];",
+                            "w = coef[e] * x[(int64_t)slot[e] * S + s0];"),
+    "lookup_constant_squared": ("w = coef[e] * x[(int64_t)slot[e] * S + s];",
+                                "w = coef[e] * coef[e] * x[(int64_t)slot[e] * S + s];"),
 }
 
 

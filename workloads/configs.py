@@ -25,7 +25,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
-from .graphs import LeveledGraph, draw_params, draw_samples, layered_graph
+from .graphs import LeveledGraph, draw_lookup, draw_params, draw_samples, draw_table, layered_graph
 
 CONFIGS = {
     "tiny": dict(widths=[1, 3, 4, 3, 1], degree=2, S=1024, x="uniform", b=(0.5, 2.0), seed=1),
@@ -44,9 +44,21 @@ def _widths(cfg) -> list:
     return [1] + [cfg["width"]] * (cfg["L"] - 1) + [1]
 
 
+def lookup_slots(L: int) -> int:
+    """Table entries per sample for a graph of L edge levels: read as order n with
+    L = 2n + 2 levels and 2n vertices, one entry per ordered vertex pair, (L - 2)^2
+    (at least 4)."""
+    return max(4, (L - 2) ** 2)
+
+
 def make_config(name: str, S: int | None = None, seed: int | None = None,
-                order: str = "src", **over) -> tuple[LeveledGraph, np.ndarray]:
-    """Build (graph, x[3,S]) for a named config.  S / seed / shape keys may be overridden."""
+                order: str = "src", factor: str = "rational", **over) -> tuple[LeveledGraph, np.ndarray]:
+    """Build (graph, per-sample input) for a named config.  S / seed / shape keys may be overridden.
+
+    factor "rational": a, b, k per edge and x[3, S] coordinates;
+    factor "lookup": the same structure with a table entry and a fermion sign per
+    edge and per-sample tables T[n_slots, S] (n_slots = lookup_slots(L)).
+    """
     cfg = dict(CONFIGS[name])
     cfg.update(over)
     if S is not None:
@@ -55,9 +67,16 @@ def make_config(name: str, S: int | None = None, seed: int | None = None,
     ss_struct, ss_par, ss_x = np.random.SeedSequence(sd).spawn(3)
     g = layered_graph(_widths(cfg), cfg["degree"], np.random.Generator(np.random.PCG64(ss_struct)),
                       order=order)
-    draw_params(g, np.random.Generator(np.random.PCG64(ss_par)), b_range=cfg["b"])
-    x = draw_samples(int(cfg["S"]), cfg["x"], np.random.Generator(np.random.PCG64(ss_x)))
-    g.meta = dict(config=name, seed=sd, **{k: v for k, v in cfg.items() if k != "seed"})
+    if factor == "lookup":
+        n_slots = int(cfg.get("n_slots", lookup_slots(g.L)))
+        g = draw_lookup(g, np.random.Generator(np.random.PCG64(ss_par)), n_slots)
+        x = draw_table(n_slots, int(cfg["S"]), np.random.Generator(np.random.PCG64(ss_x)))
+    elif factor == "rational":
+        draw_params(g, np.random.Generator(np.random.PCG64(ss_par)), b_range=cfg["b"])
+        x = draw_samples(int(cfg["S"]), cfg["x"], np.random.Generator(np.random.PCG64(ss_x)))
+    else:
+        raise ValueError(factor)
+    g.meta = dict(config=name, seed=sd, factor=factor, **{k: v for k, v in cfg.items() if k != "seed"})
     return g, x
 
 

@@ -23,8 +23,11 @@ class LeveledGraph:
     widths  int64[L+1]  node count of each level (widths[0] = widths[L] = 1)
     epl     int64[L]    edges per edge level l = 1..L (epl[l-1])
     src,dst int32[E]    global node ids, level-major
-    a, b    float64[E]  edge-factor parameters
+    a, b    float64[E]  edge-factor parameters (rational factor)
     k       float64[E,3]
+    slot    int32[E]    lookup factor: table entry of each edge (None: rational factor)
+    coef    float64[E]  lookup factor: constant of each edge (fermion-loop sign)
+    n_slots int         lookup factor: entries per sample table
     """
 
     widths: np.ndarray
@@ -35,6 +38,18 @@ class LeveledGraph:
     b: np.ndarray
     k: np.ndarray
     meta: dict = field(default_factory=dict)
+    slot: np.ndarray | None = None
+    coef: np.ndarray | None = None
+    n_slots: int = 0
+
+    @property
+    def kind(self) -> str:
+        return "lookup" if self.slot is not None else "rational"
+
+    @property
+    def n_inputs(self) -> int:
+        """Rows of the per-sample input: 3 coordinates, or the table entries."""
+        return int(self.n_slots) if self.slot is not None else 3
 
     @property
     def L(self) -> int:
@@ -59,7 +74,17 @@ class LeveledGraph:
     def copy(self) -> "LeveledGraph":
         return LeveledGraph(self.widths.copy(), self.epl.copy(), self.src.copy(),
                             self.dst.copy(), self.a.copy(), self.b.copy(),
-                            self.k.copy(), dict(self.meta))
+                            self.k.copy(), dict(self.meta),
+                            None if self.slot is None else self.slot.copy(),
+                            None if self.coef is None else self.coef.copy(), self.n_slots)
+
+    def with_lookup(self, slot, coef, n_slots: int) -> "LeveledGraph":
+        """The same structure with lookup factors w_e = coef_e * T[slot_e]."""
+        g = self.copy()
+        g.slot = np.array(np.broadcast_to(slot, (g.n_edges,)), dtype=np.int32)
+        g.coef = np.array(np.broadcast_to(coef, (g.n_edges,)), dtype=np.float64)
+        g.n_slots = int(n_slots)
+        return g
 
     def with_params(self, a=None, b=None, k=None) -> "LeveledGraph":
         g = self.copy()
@@ -182,6 +207,22 @@ def draw_params(g: LeveledGraph, rng: np.random.Generator, a_range=(-1.0, 1.0),
     return g
 
 
+def draw_lookup(g: LeveledGraph, rng: np.random.Generator, n_slots: int, p_minus: float = 0.5) -> LeveledGraph:
+    """Lookup factors: each edge reads a uniformly drawn table entry (a vertex
+    pair) and carries a sign, -1 with probability p_minus (closing a fermion
+    loop), in edge order."""
+    E = g.n_edges
+    slot = rng.integers(0, n_slots, E)
+    coef = np.where(rng.random(E) < p_minus, -1.0, 1.0)
+    return g.with_lookup(slot, coef, n_slots)
+
+
+def draw_table(n_slots: int, S: int, rng: np.random.Generator) -> np.ndarray:
+    """Per-sample tables as structure-of-arrays float64[n_slots, S], entries U[-1, 1]
+    (standing in for the Green's functions between the sample's vertices)."""
+    return rng.uniform(-1.0, 1.0, (n_slots, S))
+
+
 def draw_samples(S: int, dist: str, rng: np.random.Generator) -> np.ndarray:
     """Sample points x as structure-of-arrays float64[3, S]."""
     if dist == "uniform":
@@ -220,4 +261,6 @@ def transpose(g: LeveledGraph) -> LeveledGraph:
     idx = np.concatenate(out_idx)
     return LeveledGraph(widths_t, np.asarray(epl, dtype=np.int64),
                         np.concatenate(out_src), np.concatenate(out_dst),
-                        g.a[idx].copy(), g.b[idx].copy(), g.k[idx].copy(), dict(g.meta))
+                        g.a[idx].copy(), g.b[idx].copy(), g.k[idx].copy(), dict(g.meta),
+                        None if g.slot is None else g.slot[idx].copy(),
+                        None if g.coef is None else g.coef[idx].copy(), g.n_slots)
