@@ -14,10 +14,12 @@
  * task on a grid of blocks").
  *
  * The graph is given in the flattened form of Fig. combinedgraphflat: per edge
- * level, node-agnostic arrays of (src, dst) pairs.  The edge factor is the
- * synthetic stand-in
+ * level, node-agnostic arrays of (src, dst) pairs.  Two kinds of edge factor:
+ * the closed-form stand-in
  *       w_e(x) = a_e / (1 + b_e * |x - k_e|^2),    x, k_e in R^3,
- * for the Green's function an edge carries in the paper.
+ * for the Green's function an edge carries in the paper (cos_create_graph),
+ * and the paper's own form, a per-sample table entry times a constant,
+ *       w_e(s) = c_e * T_s[slot_e]              (cos_create_graph_lookup).
  *
  * Conventions for every entry point:
  *  - Every call returns a cos_status.  On failure cos_last_error() returns a
@@ -41,7 +43,7 @@
 extern "C" {
 #endif
 
-#define COS_ABI_VERSION 1
+#define COS_ABI_VERSION 2
 
 typedef enum cos_status {
     COS_OK = 0,
@@ -82,7 +84,13 @@ typedef struct cos_graph_info {
     int64_t max_in_degree;   /* over interior levels 1..L-1 */
     int64_t final_in_degree; /* in-edges of the final node */
     uint64_t device_bytes;   /* device memory held by the graph */
+    int32_t factor_kind;     /* COS_FACTOR_RATIONAL or COS_FACTOR_LOOKUP */
+    int32_t n_inputs;        /* rows of the per-sample input x_dev: 3, or n_slots */
 } cos_graph_info;
+
+/* Edge-factor kinds. */
+#define COS_FACTOR_RATIONAL 0 /* w_e(x) = a_e / (1 + b_e |x - k_e|^2), x the sample's point in R^3 */
+#define COS_FACTOR_LOOKUP 1   /* w_e(s) = c_e * T_s[slot_e], T_s the sample's table */
 
 /* Message for the last failed call on this thread ("" if none).  Owned by the
    library; valid until the thread's next call. */
@@ -124,6 +132,27 @@ cos_status cos_create_graph(int32_t L, const int64_t *widths, const int64_t *edg
                             const int32_t *src, const int32_t *dst, const double *a,
                             const double *b, const double *k, cos_graph **out);
 
+/*
+ * Build a graph whose edge factors are table lookups, the paper's own form
+ * (Sec. II.B: each edge multiplies by the Green's function G_ab between two of
+ * the configuration's vertices; Sec. III: per edge the tail value, that Green's
+ * function and a -1 when the edge closes a fermion loop).  Edge e multiplies
+ * its source value by coef[e] * T_s[slot[e]], where T_s is sample s's table of
+ * n_slots values given to cos_evaluate (slot = the vertex pair, coef = the
+ * sign or any other finite constant).
+ *
+ *   L, widths, edges_per_level, src, dst   as for cos_create_graph.
+ *   slot     host     int32[E], each in 0 .. n_slots-1.
+ *   coef     host     float64[E], finite.
+ *   n_slots           >= 1: entries of every sample's table.
+ *
+ * Copied like cos_create_graph; canonical order by destination, source, slot,
+ * then the bit pattern of coef.  Errors: COS_EINVAL, COS_ENOMEM, COS_EDEVICE.
+ */
+cos_status cos_create_graph_lookup(int32_t L, const int64_t *widths, const int64_t *edges_per_level,
+                                   const int32_t *src, const int32_t *dst, const int32_t *slot,
+                                   const double *coef, int32_t n_slots, cos_graph **out);
+
 /* Sizes of a graph (see cos_graph_info).  Errors: COS_EINVAL on NULL. */
 cos_status cos_graph_get_info(const cos_graph *g, cos_graph_info *info);
 
@@ -147,6 +176,11 @@ cos_status cos_graph_set_path(cos_graph *g, cos_path path);
 cos_status cos_graph_export(const cos_graph *g, int32_t *src, int32_t *dst, double *a, double *b,
                             double *k);
 
+/* The same for a lookup graph: slot int32[E], coef float64[E].  COS_EINVAL for
+   a graph with rational factors (and cos_graph_export on a lookup graph). */
+cos_status cos_graph_export_lookup(const cos_graph *g, int32_t *src, int32_t *dst, int32_t *slot,
+                                   double *coef);
+
 /*
  * Device scratch bytes cos_evaluate needs for S samples at precision p
  * (level buffers, exponent rows and final-node partial sums).
@@ -159,8 +193,10 @@ cos_status cos_evaluate_workspace_size(const cos_graph *g, int64_t S, cos_precis
  * Evaluate the final-node value for S sample points (Sec. II.B; many
  * configurations at once as in Sec. II.C).
  *
- *   x_dev        device float64[3][S]: x_dev[c*S + s] is coordinate c of
- *                sample s (structure of arrays).
+ *   x_dev        device float64[R][S], the per-sample inputs as structure of
+ *                arrays: x_dev[c*S + s] is row c of sample s.  R = 3 for
+ *                rational factors (the sample's coordinates), R = n_slots for
+ *                lookup factors (the sample's table T_s).
  *   S            >= 0 (0: nothing is queued).
  *   p            COS_FP64, COS_FP32_RESCALED or COS_FP32.
  *   out_dev      device float64[S].  Without out_exp_dev: the value V(x_s).
@@ -232,7 +268,8 @@ typedef struct cos_server_stats {
 cos_status cos_server_create(uint64_t hbm_budget, int32_t max_slots, cos_server **out);
 
 /* Register a graph (it must outlive the server) and get its id.
-   Errors: COS_EINVAL (NULL, graph on another device). */
+   Errors: COS_EINVAL (NULL, graph on another device, graph with lookup
+   factors: those are evaluated with cos_evaluate). */
 cos_status cos_server_add_graph(cos_server *srv, const cos_graph *g, int32_t *gid);
 
 /*

@@ -28,11 +28,13 @@ KINDS = {"level": 0, "fused": 1, "final_partial": 2, "final_combine": 3, "fill":
 EXPORTS = [
     "cos_last_error", "cos_build_id", "cos_abi_version", "cos_create_graph", "cos_graph_get_info",
     "cos_graph_export", "cos_evaluate_workspace_size", "cos_evaluate", "cos_destroy_graph",
-    "cos_timing_enable", "cos_timing_read", "cos_graph_set_path",
+    "cos_timing_enable", "cos_timing_read", "cos_graph_set_path", "cos_create_graph_lookup",
+    "cos_graph_export_lookup",
     "cos_server_create", "cos_server_add_graph", "cos_server_submit", "cos_server_poll", "cos_server_wait",
     "cos_server_cancel", "cos_server_get_stats", "cos_server_destroy",
 ]
 PATHS = {"auto": 0, "streamed": 1, "fused": 2}
+FACTOR_KINDS = {0: "rational", 1: "lookup"}
 
 
 class CosError(RuntimeError):
@@ -44,7 +46,8 @@ class CosError(RuntimeError):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("fused_mask", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_edges", ctypes.c_int64), ("max_width", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
-                ("final_in_degree", ctypes.c_int64), ("device_bytes", ctypes.c_uint64)]
+                ("final_in_degree", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
+                ("factor_kind", ctypes.c_int32), ("n_inputs", ctypes.c_int32)]
 
 
 class ReqStats(ctypes.Structure):
@@ -83,6 +86,10 @@ def _bind(lib):
     lib.cos_graph_get_info.argtypes = [p, ctypes.POINTER(GraphInfo)]
     lib.cos_graph_export.restype = i32
     lib.cos_graph_export.argtypes = [p, p, p, p, p, p]
+    lib.cos_create_graph_lookup.restype = i32
+    lib.cos_create_graph_lookup.argtypes = [i32, p, p, p, p, p, p, i32, ctypes.POINTER(p)]
+    lib.cos_graph_export_lookup.restype = i32
+    lib.cos_graph_export_lookup.argtypes = [p, p, p, p, p]
     lib.cos_graph_set_path.restype = i32
     lib.cos_graph_set_path.argtypes = [p, i32]
     lib.cos_evaluate_workspace_size.restype = i32

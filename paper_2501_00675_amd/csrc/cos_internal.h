@@ -44,6 +44,23 @@ static_assert(sizeof(EdgeRec32) == 32, "EdgeRec32 layout");
 // so that kernels may fetch records in fixed-size chunks without bounds tests.
 constexpr int kEdgePad = 8;
 
+// Lookup edge record (32 bytes): w_e(s) = coef * T_s[slot], the per-sample
+// table T given at evaluation as rows [slot][sample]; coef in binary64 and
+// rounded to binary32, same source index and row flags as EdgeRec.
+struct alignas(16) EdgeRecL {
+    double coef;
+    float coef32;
+    int32_t slot;
+    int32_t src;
+    int32_t row_end;
+    int32_t zero_rows;
+    int32_t unused;
+};
+static_assert(sizeof(EdgeRecL) == 32, "EdgeRecL layout");
+
+// Edge-factor kinds (cos_graph_info.factor_kind).
+enum FactorKind : int32_t { FK_RATIONAL = 0, FK_LOOKUP = 1 };
+
 // Per edge level l = 1..L (stored at index l-1).
 struct LevelDesc {
     int64_t w_src;     // widths[l-1]
@@ -63,6 +80,8 @@ struct LevelDev {
 };
 
 struct Graph {
+    int32_t kind = FK_RATIONAL;       // edge-factor kind
+    int32_t n_slots = 0;              // lookup: entries of each sample's table
     int32_t L = 0;
     std::vector<int64_t> widths;      // L+1
     std::vector<int64_t> level_first; // L+2, first global node id of each level
@@ -72,13 +91,16 @@ struct Graph {
     int64_t max_in_degree = 0;        // interior levels 1..L-1
     // canonical host copy (for export)
     std::vector<int32_t> h_src, h_dst;
-    std::vector<double> h_a, h_b, h_k;
+    std::vector<double> h_a, h_b, h_k;       // rational factors
+    std::vector<int32_t> h_slot;              // lookup factors
+    std::vector<double> h_coef;
     // device copies
     void *d_base = nullptr;
     size_t d_bytes = 0;
     int32_t *d_row_ptr = nullptr;     // global edge indices, per level w_dst+1 entries
     EdgeRec *d_edges = nullptr;       // binary64 records (binary64 sweeps, every final node)
     EdgeRec32 *d_edges32 = nullptr;   // binary32 records (interior levels of the binary32 sweeps)
+    EdgeRecL *d_edgesL = nullptr;     // lookup records (every level, every precision)
     LevelDev *d_levels = nullptr;     // L entries
     int device = 0;
     cos_path path = COS_PATH_AUTO;    // kernel plan chosen by cos_graph_set_path

@@ -162,195 +162,276 @@ cos_status validate_shape(int32_t L, const int64_t *widths, const int64_t *epl, 
 
 }  // namespace
 
+namespace {
+
+// Edge parameters of one of the two factor kinds.
+struct EdgeParams {
+    int32_t kind = FK_RATIONAL;
+    const double *a = nullptr, *b = nullptr, *k = nullptr;  // rational
+    const int32_t *slot = nullptr;                           // lookup
+    const double *coef = nullptr;
+    int32_t n_slots = 0;
+};
+
+cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_per_level, const int32_t *src,
+                       const int32_t *dst, const EdgeParams &P, cos_graph **out) {
+    if (!out)
+        return fail(COS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int64_t n_nodes = 0, n_edges = 0;
+    cos_status st = validate_shape(L, widths, edges_per_level, &n_nodes, &n_edges);
+    if (st != COS_OK)
+        return st;
+    const bool lookup = P.kind == FK_LOOKUP;
+    if (lookup && P.n_slots < 1)
+        return fail(COS_EINVAL, "n_slots must be >= 1");
+    if (n_edges > 0 && (!src || !dst || (lookup ? (!P.slot || !P.coef) : (!P.a || !P.b || !P.k))))
+        return fail(COS_EINVAL, "edge arrays are NULL");
+
+    auto h = std::make_unique<cos_graph>();
+    Graph &G = h->g;
+    G.kind = P.kind;
+    G.n_slots = lookup ? P.n_slots : 0;
+    G.L = L;
+    G.widths.assign(widths, widths + L + 1);
+    G.level_first.resize(L + 2);
+    G.level_first[0] = 0;
+    for (int32_t l = 0; l <= L; ++l)
+        G.level_first[l + 1] = G.level_first[l] + widths[l];
+    G.n_nodes = n_nodes;
+    G.n_edges = n_edges;
+
+    // validate every edge against its level and its parameters
+    int64_t e = 0;
+    for (int32_t l = 1; l <= L; ++l) {
+        const int64_t s_lo = G.level_first[l - 1], s_hi = G.level_first[l];
+        const int64_t d_lo = G.level_first[l], d_hi = G.level_first[l + 1];
+        for (int64_t i = 0; i < edges_per_level[l - 1]; ++i, ++e) {
+            if (src[e] < s_lo || src[e] >= s_hi || dst[e] < d_lo || dst[e] >= d_hi)
+                return fail(COS_EINVAL, "edge " + std::to_string(e) + " (" + std::to_string(src[e]) + "->" +
+                                            std::to_string(dst[e]) + ") does not join level " +
+                                            std::to_string(l - 1) + " to level " + std::to_string(l));
+            if (lookup) {
+                if (P.slot[e] < 0 || P.slot[e] >= P.n_slots || !std::isfinite(P.coef[e]))
+                    return fail(COS_EINVAL, "edge " + std::to_string(e) +
+                                                ": slot must be in 0..n_slots-1 and the constant finite");
+            } else if (!std::isfinite(P.a[e]) || !std::isfinite(P.b[e]) || P.b[e] < 0.0 ||
+                       !std::isfinite(P.k[3 * e]) || !std::isfinite(P.k[3 * e + 1]) ||
+                       !std::isfinite(P.k[3 * e + 2])) {
+                return fail(COS_EINVAL, "edge " + std::to_string(e) + ": parameters must be finite with b >= 0");
+            }
+        }
+    }
+
+    // canonical order within each level: (dst, src, then the parameters:
+    // bits of a, b, k0, k1, k2 -- or the slot and the bits of the constant)
+    std::vector<int64_t> order(n_edges);
+    std::iota(order.begin(), order.end(), 0);
+    G.levels.resize(L);
+    int64_t e0 = 0, rp = 0;
+    for (int32_t l = 1; l <= L; ++l) {
+        const int64_t ne = edges_per_level[l - 1];
+        auto less = [&](int64_t i, int64_t j) {
+            if (dst[i] != dst[j])
+                return dst[i] < dst[j];
+            if (src[i] != src[j])
+                return src[i] < src[j];
+            if (lookup) {
+                if (P.slot[i] != P.slot[j])
+                    return P.slot[i] < P.slot[j];
+                return bits_of(P.coef[i]) < bits_of(P.coef[j]);
+            }
+            const double pi[5] = {P.a[i], P.b[i], P.k[3 * i], P.k[3 * i + 1], P.k[3 * i + 2]};
+            const double pj[5] = {P.a[j], P.b[j], P.k[3 * j], P.k[3 * j + 1], P.k[3 * j + 2]};
+            for (int c = 0; c < 5; ++c)
+                if (bits_of(pi[c]) != bits_of(pj[c]))
+                    return bits_of(pi[c]) < bits_of(pj[c]);
+            return false;
+        };
+        std::sort(order.begin() + e0, order.begin() + e0 + ne, less);
+        LevelDesc &d = G.levels[l - 1];
+        d.w_src = widths[l - 1];
+        d.w_dst = widths[l];
+        d.e_begin = e0;
+        d.n_edges = ne;
+        d.rp_begin = rp;
+        rp += d.w_dst + 1;
+        e0 += ne;
+    }
+
+    G.h_src.resize(n_edges);
+    G.h_dst.resize(n_edges);
+    if (lookup) {
+        G.h_slot.resize(n_edges);
+        G.h_coef.resize(n_edges);
+    } else {
+        G.h_a.resize(n_edges);
+        G.h_b.resize(n_edges);
+        G.h_k.resize(3 * n_edges);
+    }
+    for (int64_t i = 0; i < n_edges; ++i) {
+        const int64_t o = order[i];
+        G.h_src[i] = src[o];
+        G.h_dst[i] = dst[o];
+        if (lookup) {
+            G.h_slot[i] = P.slot[o];
+            G.h_coef[i] = P.coef[o];
+        } else {
+            G.h_a[i] = P.a[o];
+            G.h_b[i] = P.b[o];
+            G.h_k[3 * i] = P.k[3 * o];
+            G.h_k[3 * i + 1] = P.k[3 * o + 1];
+            G.h_k[3 * i + 2] = P.k[3 * o + 2];
+        }
+    }
+    order.clear();
+    order.shrink_to_fit();
+
+    // per-level CSR over destinations (global edge indices) and edge records
+    std::vector<int32_t> row_ptr(rp);
+    std::vector<EdgeRec> recs(lookup ? 0 : n_edges + kEdgePad, EdgeRec{});
+    std::vector<EdgeRec32> recs32(lookup ? 0 : n_edges + kEdgePad, EdgeRec32{});
+    std::vector<EdgeRecL> recsL(lookup ? n_edges + kEdgePad : 0, EdgeRecL{});
+    std::vector<LevelDev> ldev(L);
+    for (int32_t l = 1; l <= L; ++l) {
+        LevelDesc &d = G.levels[l - 1];
+        int32_t *r = row_ptr.data() + d.rp_begin;
+        const int64_t dfirst = G.level_first[l], sfirst = G.level_first[l - 1];
+        int64_t i = d.e_begin, maxdeg = 0;
+        for (int64_t j = 0; j < d.w_dst; ++j) {
+            r[j] = static_cast<int32_t>(i);
+            const int64_t start = i;
+            while (i < d.e_begin + d.n_edges && G.h_dst[i] == dfirst + j)
+                ++i;
+            maxdeg = std::max(maxdeg, i - start);
+        }
+        r[d.w_dst] = static_cast<int32_t>(i);
+        d.max_deg = maxdeg;
+        if (l < L) {
+            G.max_width = std::max(G.max_width, d.w_dst);
+            G.max_in_degree = std::max(G.max_in_degree, maxdeg);
+        }
+        for (int64_t q = d.e_begin; q < d.e_begin + d.n_edges; ++q) {
+            const int32_t src_local = static_cast<int32_t>(G.h_src[q] - sfirst);
+            if (lookup) {
+                EdgeRecL &rl = recsL[q];
+                rl.coef = G.h_coef[q];
+                rl.coef32 = static_cast<float>(G.h_coef[q]);
+                rl.slot = G.h_slot[q];
+                rl.src = src_local;
+                continue;
+            }
+            const double b = G.h_b[q], k0 = G.h_k[3 * q], k1 = G.h_k[3 * q + 1], k2 = G.h_k[3 * q + 2];
+            EdgeRec &rec = recs[q];
+            rec.c0 = 1.0 + b * (k0 * k0 + k1 * k1 + k2 * k2);
+            rec.cb = b;
+            rec.g0 = -2.0 * b * k0;
+            rec.g1 = -2.0 * b * k1;
+            rec.g2 = -2.0 * b * k2;
+            rec.a = G.h_a[q];
+            rec.src = src_local;
+            EdgeRec32 &r32 = recs32[q];
+            r32.a = static_cast<float>(G.h_a[q]);
+            r32.b = static_cast<float>(b);
+            r32.k0 = static_cast<float>(k0);
+            r32.k1 = static_cast<float>(k1);
+            r32.k2 = static_cast<float>(k2);
+            r32.src = src_local;
+        }
+        // row boundaries inside the edge stream: the last edge of every
+        // non-empty row, and how many empty rows follow it
+        for (int64_t j = 0; j < d.w_dst; ++j) {
+            if (r[j + 1] == r[j])
+                continue;
+            int64_t z = j + 1;
+            while (z < d.w_dst && r[z + 1] == r[z])
+                ++z;
+            const int64_t last = r[j + 1] - 1;
+            const int32_t zr = static_cast<int32_t>(z - (j + 1));
+            if (lookup) {
+                recsL[last].row_end = 1;
+                recsL[last].zero_rows = zr;
+            } else {
+                recs[last].row_end = 1;
+                recs[last].zero_rows = zr;
+                recs32[last].row_end = 1;
+                recs32[last].zero_rows = zr;
+            }
+        }
+        ldev[l - 1] = LevelDev{static_cast<int32_t>(d.w_dst), static_cast<int32_t>(d.rp_begin),
+                               static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges)};
+    }
+
+    // one device allocation: row_ptr | edge record arrays | level table
+    const size_t off_rp = 0;
+    const size_t off_rec = round_up(rp * sizeof(int32_t), 256);
+    const size_t off_rec32 = off_rec + round_up(recs.size() * sizeof(EdgeRec), 256);
+    const size_t off_recL = off_rec32 + round_up(recs32.size() * sizeof(EdgeRec32), 256);
+    const size_t off_lev = off_recL + round_up(recsL.size() * sizeof(EdgeRecL), 256);
+    const size_t total = off_lev + round_up(L * sizeof(LevelDev), 256);
+    hipError_t err = hipGetDevice(&G.device);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipGetDevice");
+    err = hipMalloc(&G.d_base, total);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipMalloc(graph)");
+    G.d_bytes = total;
+    char *base = static_cast<char *>(G.d_base);
+    G.d_row_ptr = reinterpret_cast<int32_t *>(base + off_rp);
+    G.d_edges = lookup ? nullptr : reinterpret_cast<EdgeRec *>(base + off_rec);
+    G.d_edges32 = lookup ? nullptr : reinterpret_cast<EdgeRec32 *>(base + off_rec32);
+    G.d_edgesL = lookup ? reinterpret_cast<EdgeRecL *>(base + off_recL) : nullptr;
+    G.d_levels = reinterpret_cast<LevelDev *>(base + off_lev);
+    err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (err == hipSuccess && !recs.empty())
+        err = hipMemcpy(G.d_edges, recs.data(), recs.size() * sizeof(EdgeRec), hipMemcpyHostToDevice);
+    if (err == hipSuccess && !recs32.empty())
+        err = hipMemcpy(G.d_edges32, recs32.data(), recs32.size() * sizeof(EdgeRec32), hipMemcpyHostToDevice);
+    if (err == hipSuccess && !recsL.empty())
+        err = hipMemcpy(G.d_edgesL, recsL.data(), recsL.size() * sizeof(EdgeRecL), hipMemcpyHostToDevice);
+    if (err == hipSuccess)
+        err = hipMemcpy(G.d_levels, ldev.data(), L * sizeof(LevelDev), hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(G.d_base);
+        return hip_fail(err, "hipMemcpy(graph)");
+    }
+    *out = h.release();
+    return COS_OK;
+}
+
+}  // namespace
+
 extern "C" cos_status cos_create_graph(int32_t L, const int64_t *widths, const int64_t *edges_per_level,
                                        const int32_t *src, const int32_t *dst, const double *a,
                                        const double *b, const double *k, cos_graph **out) {
     try {
-        if (!out)
-            return fail(COS_EINVAL, "out is NULL");
-        *out = nullptr;
-        int64_t n_nodes = 0, n_edges = 0;
-        cos_status st = validate_shape(L, widths, edges_per_level, &n_nodes, &n_edges);
-        if (st != COS_OK)
-            return st;
-        if (n_edges > 0 && (!src || !dst || !a || !b || !k))
-            return fail(COS_EINVAL, "edge arrays are NULL");
-
-        auto h = std::make_unique<cos_graph>();
-        Graph &G = h->g;
-        G.L = L;
-        G.widths.assign(widths, widths + L + 1);
-        G.level_first.resize(L + 2);
-        G.level_first[0] = 0;
-        for (int32_t l = 0; l <= L; ++l)
-            G.level_first[l + 1] = G.level_first[l] + widths[l];
-        G.n_nodes = n_nodes;
-        G.n_edges = n_edges;
-
-        // validate every edge against its level and its parameters
-        int64_t e = 0;
-        for (int32_t l = 1; l <= L; ++l) {
-            const int64_t s_lo = G.level_first[l - 1], s_hi = G.level_first[l];
-            const int64_t d_lo = G.level_first[l], d_hi = G.level_first[l + 1];
-            for (int64_t i = 0; i < edges_per_level[l - 1]; ++i, ++e) {
-                if (src[e] < s_lo || src[e] >= s_hi || dst[e] < d_lo || dst[e] >= d_hi)
-                    return fail(COS_EINVAL, "edge " + std::to_string(e) + " (" + std::to_string(src[e]) + "->" +
-                                                std::to_string(dst[e]) + ") does not join level " +
-                                                std::to_string(l - 1) + " to level " + std::to_string(l));
-                if (!std::isfinite(a[e]) || !std::isfinite(b[e]) || b[e] < 0.0 || !std::isfinite(k[3 * e]) ||
-                    !std::isfinite(k[3 * e + 1]) || !std::isfinite(k[3 * e + 2]))
-                    return fail(COS_EINVAL, "edge " + std::to_string(e) +
-                                                ": parameters must be finite with b >= 0");
-            }
-        }
-
-        // canonical order within each level: (dst, src, bits of a, b, k0, k1, k2)
-        std::vector<int64_t> order(n_edges);
-        std::iota(order.begin(), order.end(), 0);
-        G.levels.resize(L);
-        int64_t e0 = 0, rp = 0;
-        for (int32_t l = 1; l <= L; ++l) {
-            const int64_t ne = edges_per_level[l - 1];
-            auto less = [&](int64_t i, int64_t j) {
-                if (dst[i] != dst[j])
-                    return dst[i] < dst[j];
-                if (src[i] != src[j])
-                    return src[i] < src[j];
-                const double pi[5] = {a[i], b[i], k[3 * i], k[3 * i + 1], k[3 * i + 2]};
-                const double pj[5] = {a[j], b[j], k[3 * j], k[3 * j + 1], k[3 * j + 2]};
-                for (int c = 0; c < 5; ++c)
-                    if (bits_of(pi[c]) != bits_of(pj[c]))
-                        return bits_of(pi[c]) < bits_of(pj[c]);
-                return false;
-            };
-            std::sort(order.begin() + e0, order.begin() + e0 + ne, less);
-            LevelDesc &d = G.levels[l - 1];
-            d.w_src = widths[l - 1];
-            d.w_dst = widths[l];
-            d.e_begin = e0;
-            d.n_edges = ne;
-            d.rp_begin = rp;
-            rp += d.w_dst + 1;
-            e0 += ne;
-        }
-
-        G.h_src.resize(n_edges);
-        G.h_dst.resize(n_edges);
-        G.h_a.resize(n_edges);
-        G.h_b.resize(n_edges);
-        G.h_k.resize(3 * n_edges);
-        for (int64_t i = 0; i < n_edges; ++i) {
-            const int64_t o = order[i];
-            G.h_src[i] = src[o];
-            G.h_dst[i] = dst[o];
-            G.h_a[i] = a[o];
-            G.h_b[i] = b[o];
-            G.h_k[3 * i] = k[3 * o];
-            G.h_k[3 * i + 1] = k[3 * o + 1];
-            G.h_k[3 * i + 2] = k[3 * o + 2];
-        }
-        order.clear();
-        order.shrink_to_fit();
-
-        // per-level CSR over destinations (global edge indices) and edge records
-        std::vector<int32_t> row_ptr(rp);
-        std::vector<EdgeRec> recs(n_edges + kEdgePad, EdgeRec{});
-        std::vector<EdgeRec32> recs32(n_edges + kEdgePad, EdgeRec32{});
-        std::vector<LevelDev> ldev(L);
-        for (int32_t l = 1; l <= L; ++l) {
-            LevelDesc &d = G.levels[l - 1];
-            int32_t *r = row_ptr.data() + d.rp_begin;
-            const int64_t dfirst = G.level_first[l], sfirst = G.level_first[l - 1];
-            int64_t i = d.e_begin, maxdeg = 0;
-            for (int64_t j = 0; j < d.w_dst; ++j) {
-                r[j] = static_cast<int32_t>(i);
-                const int64_t start = i;
-                while (i < d.e_begin + d.n_edges && G.h_dst[i] == dfirst + j)
-                    ++i;
-                maxdeg = std::max(maxdeg, i - start);
-            }
-            r[d.w_dst] = static_cast<int32_t>(i);
-            d.max_deg = maxdeg;
-            if (l < L) {
-                G.max_width = std::max(G.max_width, d.w_dst);
-                G.max_in_degree = std::max(G.max_in_degree, maxdeg);
-            }
-            for (int64_t q = d.e_begin; q < d.e_begin + d.n_edges; ++q) {
-                const double b = G.h_b[q], k0 = G.h_k[3 * q], k1 = G.h_k[3 * q + 1], k2 = G.h_k[3 * q + 2];
-                EdgeRec &rec = recs[q];
-                rec.c0 = 1.0 + b * (k0 * k0 + k1 * k1 + k2 * k2);
-                rec.cb = b;
-                rec.g0 = -2.0 * b * k0;
-                rec.g1 = -2.0 * b * k1;
-                rec.g2 = -2.0 * b * k2;
-                rec.a = G.h_a[q];
-                rec.src = static_cast<int32_t>(G.h_src[q] - sfirst);
-                rec.unused = 0;
-                rec.row_end = 0;
-                rec.zero_rows = 0;
-                EdgeRec32 &r32 = recs32[q];
-                r32.a = static_cast<float>(G.h_a[q]);
-                r32.b = static_cast<float>(b);
-                r32.k0 = static_cast<float>(k0);
-                r32.k1 = static_cast<float>(k1);
-                r32.k2 = static_cast<float>(k2);
-                r32.src = rec.src;
-                r32.row_end = 0;
-                r32.zero_rows = 0;
-            }
-            // row boundaries inside the edge stream: the last edge of every
-            // non-empty row, and how many empty rows follow it
-            for (int64_t j = 0; j < d.w_dst; ++j) {
-                if (r[j + 1] == r[j])
-                    continue;
-                EdgeRec &last = recs[r[j + 1] - 1];
-                last.row_end = 1;
-                int64_t z = j + 1;
-                while (z < d.w_dst && r[z + 1] == r[z])
-                    ++z;
-                last.zero_rows = static_cast<int32_t>(z - (j + 1));
-                recs32[r[j + 1] - 1].row_end = 1;
-                recs32[r[j + 1] - 1].zero_rows = last.zero_rows;
-            }
-            ldev[l - 1] = LevelDev{static_cast<int32_t>(d.w_dst), static_cast<int32_t>(d.rp_begin),
-                                   static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges)};
-        }
-
-        // one device allocation: row_ptr | edge records | binary32 edge records | level table
-        const size_t off_rp = 0;
-        const size_t off_rec = round_up(rp * sizeof(int32_t), 256);
-        const size_t off_rec32 = off_rec + round_up((n_edges + kEdgePad) * sizeof(EdgeRec), 256);
-        const size_t off_lev = off_rec32 + round_up((n_edges + kEdgePad) * sizeof(EdgeRec32), 256);
-        const size_t total = off_lev + round_up(L * sizeof(LevelDev), 256);
-        hipError_t err = hipGetDevice(&G.device);
-        if (err != hipSuccess)
-            return hip_fail(err, "hipGetDevice");
-        err = hipMalloc(&G.d_base, total);
-        if (err != hipSuccess)
-            return hip_fail(err, "hipMalloc(graph)");
-        G.d_bytes = total;
-        char *base = static_cast<char *>(G.d_base);
-        G.d_row_ptr = reinterpret_cast<int32_t *>(base + off_rp);
-        G.d_edges = reinterpret_cast<EdgeRec *>(base + off_rec);
-        G.d_edges32 = reinterpret_cast<EdgeRec32 *>(base + off_rec32);
-        G.d_levels = reinterpret_cast<LevelDev *>(base + off_lev);
-        err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
-        if (err == hipSuccess)
-            err = hipMemcpy(G.d_edges, recs.data(), recs.size() * sizeof(EdgeRec), hipMemcpyHostToDevice);
-        if (err == hipSuccess)
-            err = hipMemcpy(G.d_edges32, recs32.data(), recs32.size() * sizeof(EdgeRec32), hipMemcpyHostToDevice);
-        if (err == hipSuccess)
-            err = hipMemcpy(G.d_levels, ldev.data(), L * sizeof(LevelDev), hipMemcpyHostToDevice);
-        if (err != hipSuccess) {
-            (void)hipFree(G.d_base);
-            return hip_fail(err, "hipMemcpy(graph)");
-        }
-        *out = h.release();
-        return COS_OK;
+        EdgeParams P;
+        P.kind = FK_RATIONAL;
+        P.a = a;
+        P.b = b;
+        P.k = k;
+        return build_graph(L, widths, edges_per_level, src, dst, P, out);
     } catch (const std::bad_alloc &) {
         return fail(COS_ENOMEM, "host allocation failed in cos_create_graph");
     } catch (...) {
         return fail(COS_EDEVICE, "unexpected exception in cos_create_graph");
+    }
+}
+
+extern "C" cos_status cos_create_graph_lookup(int32_t L, const int64_t *widths, const int64_t *edges_per_level,
+                                              const int32_t *src, const int32_t *dst, const int32_t *slot,
+                                              const double *coef, int32_t n_slots, cos_graph **out) {
+    try {
+        EdgeParams P;
+        P.kind = FK_LOOKUP;
+        P.slot = slot;
+        P.coef = coef;
+        P.n_slots = n_slots;
+        return build_graph(L, widths, edges_per_level, src, dst, P, out);
+    } catch (const std::bad_alloc &) {
+        return fail(COS_ENOMEM, "host allocation failed in cos_create_graph_lookup");
+    } catch (...) {
+        return fail(COS_EDEVICE, "unexpected exception in cos_create_graph_lookup");
     }
 }
 
@@ -367,6 +448,8 @@ extern "C" cos_status cos_graph_get_info(const cos_graph *h, cos_graph_info *inf
     info->max_in_degree = G.max_in_degree;
     info->final_in_degree = G.levels.back().n_edges;
     info->device_bytes = G.d_bytes;
+    info->factor_kind = G.kind;
+    info->n_inputs = G.kind == FK_LOOKUP ? G.n_slots : 3;
     return COS_OK;
 }
 
@@ -384,12 +467,29 @@ extern "C" cos_status cos_graph_export(const cos_graph *h, int32_t *src, int32_t
     if (!h || !src || !dst || !a || !b || !k)
         return fail(COS_EINVAL, "cos_graph_export: NULL argument");
     const Graph &G = h->g;
+    if (G.kind != FK_RATIONAL)
+        return fail(COS_EINVAL, "cos_graph_export: the graph has lookup factors (use cos_graph_export_lookup)");
     const size_t n = static_cast<size_t>(G.n_edges);
     std::memcpy(src, G.h_src.data(), n * sizeof(int32_t));
     std::memcpy(dst, G.h_dst.data(), n * sizeof(int32_t));
     std::memcpy(a, G.h_a.data(), n * sizeof(double));
     std::memcpy(b, G.h_b.data(), n * sizeof(double));
     std::memcpy(k, G.h_k.data(), 3 * n * sizeof(double));
+    return COS_OK;
+}
+
+extern "C" cos_status cos_graph_export_lookup(const cos_graph *h, int32_t *src, int32_t *dst, int32_t *slot,
+                                              double *coef) {
+    if (!h || !src || !dst || !slot || !coef)
+        return fail(COS_EINVAL, "cos_graph_export_lookup: NULL argument");
+    const Graph &G = h->g;
+    if (G.kind != FK_LOOKUP)
+        return fail(COS_EINVAL, "cos_graph_export_lookup: the graph has rational factors (use cos_graph_export)");
+    const size_t n = static_cast<size_t>(G.n_edges);
+    std::memcpy(src, G.h_src.data(), n * sizeof(int32_t));
+    std::memcpy(dst, G.h_dst.data(), n * sizeof(int32_t));
+    std::memcpy(slot, G.h_slot.data(), n * sizeof(int32_t));
+    std::memcpy(coef, G.h_coef.data(), n * sizeof(double));
     return COS_OK;
 }
 

@@ -65,9 +65,9 @@ __device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group,
 // RESCALE: the rows are scaled by 2^-e_{l-1}[s], e_{l-1}[s] = ilogb of the
 // largest |value| of level l-1 for sample s (read from prev_max), and the
 // largest |value| of this level is folded into cur_max[s].
-template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE>
+template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE, int KIND>
 __global__ __launch_bounds__(kBlock) void level_gather_kernel(
-    const int32_t *__restrict__ row_ptr, const typename SweepPath<T>::Rec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
+    const int32_t *__restrict__ row_ptr, const typename SweepPath<T, KIND>::Rec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
     int32_t n_tiles, int32_t xcd_group, int32_t reverse_tiles, const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
     const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
     uint32_t *__restrict__ cur_max) {
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
-    typename SweepPath<T>::template Samples<K> smp;
+    typename SweepPath<T, KIND>::template Samples<K> smp;
     smp.load(x, S, xs, tbase, lane);
     int esh[K];
     uint32_t lmax[K];
@@ -88,8 +88,8 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     }
     const int jbeg = min(rg * (4 * ROWS) + wave * ROWS, w_dst);
     const int jend = min(jbeg + ROWS, w_dst);
-    level_wave_rows<T, K, FROM_ROOT, RESCALE>(row_ptr, edges, jbeg, jend, prev, cur, ld, tbase, lane, smp, esh,
-                                              lmax);
+    level_wave_rows<T, K, FROM_ROOT, RESCALE, KIND>(row_ptr, edges, jbeg, jend, prev, cur, ld, tbase, lane, smp,
+                                                    esh, lmax);
     if constexpr (RESCALE) {
         if (cur_max) {
             __shared__ uint32_t red[4 * kWave * K];
@@ -101,22 +101,22 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
 // Final node, pass 1: block (sample tile, chunk c) sums the edges of chunk c
 // (kFinalChunk edges) in binary64; wave w takes the w-th quarter of the chunk;
 // the four wave sums are added as ((q0 + q1) + q2) + q3 into partial[c][s].
-template <typename TV, int K, bool FROM_ROOT>
+template <typename TV, int K, bool FROM_ROOT, int KIND>
 __global__ __launch_bounds__(kBlock) void final_partial_kernel(
-    const EdgeRec *__restrict__ edges, int32_t n_edges, int32_t n_chunks, const TV *__restrict__ prev, int64_t ld,
+    const typename FinalPath<KIND>::Rec *__restrict__ edges, int32_t n_edges, int32_t n_chunks, const TV *__restrict__ prev, int64_t ld,
     const double *__restrict__ x, int64_t S, int64_t xs, double *__restrict__ partial) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = blockIdx.x / n_chunks;
     const int c = blockIdx.x - tile * n_chunks;
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
-    LaneSamples<K> smp;
+    typename FinalPath<KIND>::template Samples<K> smp;
     smp.load(x, S, xs, tbase, lane);
     const int c_end = min((c + 1) * kFinalChunk, n_edges);
     const int e_lo = min(c * kFinalChunk + wave * kQuarter, c_end);
     const int e_hi = min(e_lo + kQuarter, c_end);
     double acc[K];
-    final_quarter<TV, K, FROM_ROOT>(edges, e_lo, e_hi, prev, ld, tbase, lane, smp, acc);
+    final_quarter<TV, K, FROM_ROOT, KIND>(edges, e_lo, e_hi, prev, ld, tbase, lane, smp, acc);
     __shared__ double red[4][kWave * K];
 #pragma unroll
     for (int m = 0; m < K; ++m)
@@ -161,7 +161,7 @@ int level_k(int64_t w_src) {
     return fits(2) ? 2 : 4;
 }
 
-template <typename T, int K, bool RESCALE>
+template <typename T, int K, bool RESCALE, int KIND>
 hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
                           int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
     const LevelDesc &d = g.levels[l - 1];
@@ -176,19 +176,21 @@ hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, in
     if (grid > INT32_MAX)
         return hipErrorInvalidConfiguration;
     const int32_t *rp = g.d_row_ptr + d.rp_begin;
-    const typename SweepPath<T>::Rec *recs;
-    if constexpr (sizeof(T) == sizeof(double))
+    const typename SweepPath<T, KIND>::Rec *recs;
+    if constexpr (KIND == FK_LOOKUP)
+        recs = g.d_edgesL;
+    else if constexpr (sizeof(T) == sizeof(double))
         recs = g.d_edges;
     else
         recs = g.d_edges32;
     TimedLaunch tl(KK_LEVEL, s);
     if (prev == nullptr)
-        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, true, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
+        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, true, RESCALE, KIND>), dim3(grid), dim3(kBlock), 0, s, rp,
                            recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
                            static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, nullptr, static_cast<T *>(cur), ld,
                            x, S, xs, prev_max, cur_max);
     else
-        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, false, RESCALE>), dim3(grid), dim3(kBlock), 0, s, rp,
+        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, false, RESCALE, KIND>), dim3(grid), dim3(kBlock), 0, s, rp,
                            recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
                            static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, static_cast<const T *>(prev),
                            static_cast<T *>(cur), ld, x, S, xs, prev_max, cur_max);
@@ -198,9 +200,12 @@ hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, in
 template <typename T, bool RESCALE>
 hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
                           int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
-    if (level_k<T>(g.levels[l - 1].w_src) == 2)
-        return launch_level_k<T, 2, RESCALE>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
-    return launch_level_k<T, 4, RESCALE>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
+    const bool k2 = level_k<T>(g.levels[l - 1].w_src) == 2;
+    if (g.kind == FK_LOOKUP)
+        return k2 ? launch_level_k<T, 2, RESCALE, FK_LOOKUP>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s)
+                  : launch_level_k<T, 4, RESCALE, FK_LOOKUP>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
+    return k2 ? launch_level_k<T, 2, RESCALE, FK_RATIONAL>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s)
+              : launch_level_k<T, 4, RESCALE, FK_RATIONAL>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
 }
 
 }  // namespace
@@ -223,29 +228,43 @@ hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev
     return hipErrorInvalidValue;
 }
 
+namespace {
+
+template <int KIND>
+hipError_t launch_final_partial(const Graph &g, cos_precision p, const void *prev, int64_t ld, const double *x,
+                                int64_t S, int64_t xs, double *partial, int32_t chunks, hipStream_t s) {
+    const LevelDesc &d = g.levels[g.L - 1];
+    const int64_t n_tiles = ld / (kWave * kKFinal);
+    const typename FinalPath<KIND>::Rec *edges;
+    if constexpr (KIND == FK_LOOKUP)
+        edges = g.d_edgesL + d.e_begin;
+    else
+        edges = g.d_edges + d.e_begin;
+    const int32_t ne = static_cast<int32_t>(d.n_edges);
+    TimedLaunch tl(KK_FINAL_PARTIAL, s);
+    const dim3 grid(static_cast<unsigned>(n_tiles * chunks));
+    if (prev == nullptr)
+        hipLaunchKernelGGL((final_partial_kernel<double, kKFinal, true, KIND>), grid, dim3(kBlock), 0, s, edges, ne,
+                           chunks, static_cast<const double *>(nullptr), ld, x, S, xs, partial);
+    else if (p == COS_FP64)
+        hipLaunchKernelGGL((final_partial_kernel<double, kKFinal, false, KIND>), grid, dim3(kBlock), 0, s, edges, ne,
+                           chunks, static_cast<const double *>(prev), ld, x, S, xs, partial);
+    else
+        hipLaunchKernelGGL((final_partial_kernel<float, kKFinal, false, KIND>), grid, dim3(kBlock), 0, s, edges, ne,
+                           chunks, static_cast<const float *>(prev), ld, x, S, xs, partial);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld, const double *x, int64_t S,
                         int64_t xs, const uint32_t *maxbits, double *partial, int32_t chunks, double *out,
                         int32_t *out_exp, hipStream_t s) {
-    const LevelDesc &d = g.levels[g.L - 1];
-    const int64_t n_tiles = ld / (kWave * kKFinal);
-    const EdgeRec *edges = g.d_edges + d.e_begin;
-    const int32_t ne = static_cast<int32_t>(d.n_edges);
-    {
-        TimedLaunch tl(KK_FINAL_PARTIAL, s);
-        const dim3 grid(static_cast<unsigned>(n_tiles * chunks));
-        if (prev == nullptr)
-            hipLaunchKernelGGL((final_partial_kernel<double, kKFinal, true>), grid, dim3(kBlock), 0, s, edges, ne,
-                               chunks, static_cast<const double *>(nullptr), ld, x, S, xs, partial);
-        else if (p == COS_FP64)
-            hipLaunchKernelGGL((final_partial_kernel<double, kKFinal, false>), grid, dim3(kBlock), 0, s, edges, ne,
-                               chunks, static_cast<const double *>(prev), ld, x, S, xs, partial);
-        else
-            hipLaunchKernelGGL((final_partial_kernel<float, kKFinal, false>), grid, dim3(kBlock), 0, s, edges, ne,
-                               chunks, static_cast<const float *>(prev), ld, x, S, xs, partial);
-        hipError_t err = hipGetLastError();
-        if (err != hipSuccess)
-            return err;
-    }
+    hipError_t err = g.kind == FK_LOOKUP
+                         ? launch_final_partial<FK_LOOKUP>(g, p, prev, ld, x, S, xs, partial, chunks, s)
+                         : launch_final_partial<FK_RATIONAL>(g, p, prev, ld, x, S, xs, partial, chunks, s);
+    if (err != hipSuccess)
+        return err;
     TimedLaunch tl(KK_FINAL_COMBINE, s);
     const dim3 grid(static_cast<unsigned>((S + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(final_combine_kernel, grid, dim3(kBlock), 0, s, partial, chunks, ld, S,

@@ -41,8 +41,8 @@ template <typename T, int RMAX, bool RESCALE>
 __device__ __forceinline__ void serve_fused(const ServeReqDev &r, uint32_t tile, unsigned char *lds, int wave,
                                             int lane) {
     if constexpr (acc_fits(sizeof(T), 1, RMAX)) {
-        const FusedGraph G{r.row_ptr, r.edges, r.edges32, r.levels, r.L, r.x, r.S, r.out, r.out_exp};
-        fused_tile<T, 1, RMAX, RESCALE>(G, static_cast<int64_t>(tile) * kWave, reinterpret_cast<T *>(lds),
+        const FusedGraph G{r.row_ptr, r.edges, r.edges32, nullptr, r.levels, r.L, r.x, r.S, r.out, r.out_exp};
+        fused_tile<T, 1, RMAX, RESCALE, FK_RATIONAL>(G, static_cast<int64_t>(tile) * kWave, reinterpret_cast<T *>(lds),
                                         reinterpret_cast<uint32_t *>(lds + r.off_red),
                                         reinterpret_cast<double *>(lds + r.off_part), wave, lane);
     }
@@ -88,9 +88,9 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     T *cur = (l - 1) & 1 ? b1 : b0;
     const T *prev = (l - 2) & 1 ? b1 : b0;
     uint32_t *maxbits = reinterpret_cast<uint32_t *>(r.ws + r.off_maxbits);
-    typename SweepPath<T>::template Samples<K> smp;
+    typename SweepPath<T, FK_RATIONAL>::template Samples<K> smp;
     smp.load(r.x, r.S, r.S, tbase, lane);
-    const typename SweepPath<T>::Rec *recs;
+    const typename SweepPath<T, FK_RATIONAL>::Rec *recs;
     if constexpr (sizeof(T) == sizeof(double))
         recs = r.edges;
     else
@@ -107,10 +107,10 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     const int jend = min(jbeg + kServeLevelRows, lv.w_dst);
     const int32_t *rp = r.row_ptr + lv.rp_begin;
     if (l == 1)
-        level_wave_rows<T, K, true, RESCALE>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
+        level_wave_rows<T, K, true, RESCALE, FK_RATIONAL>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
                                              lmax);
     else
-        level_wave_rows<T, K, false, RESCALE>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
+        level_wave_rows<T, K, false, RESCALE, FK_RATIONAL>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
                                               lmax);
     if constexpr (RESCALE) {
         if (l <= r.L - 2)
@@ -136,10 +136,10 @@ __device__ __forceinline__ void serve_final(const ServeReqDev &r, uint32_t local
     double acc[K];
     const EdgeRec *edges = r.edges + lf.e_begin;
     if (r.L == 1) {
-        final_quarter<double, K, true>(edges, e_lo, e_hi, nullptr, r.S_pad, tbase, lane, smp, acc);
+        final_quarter<double, K, true, FK_RATIONAL>(edges, e_lo, e_hi, nullptr, r.S_pad, tbase, lane, smp, acc);
     } else {
         const TV *prev = reinterpret_cast<const TV *>(r.ws + ((r.L - 2) & 1 ? r.off_buf1 : r.off_buf0));
-        final_quarter<TV, K, false>(edges, e_lo, e_hi, prev, r.S_pad, tbase, lane, smp, acc);
+        final_quarter<TV, K, false, FK_RATIONAL>(edges, e_lo, e_hi, prev, r.S_pad, tbase, lane, smp, acc);
     }
 #pragma unroll
     for (int m = 0; m < K; ++m)

@@ -427,6 +427,8 @@ extern "C" cos_status cos_server_add_graph(cos_server *h, const cos_graph *g, in
     const Graph &G = graph_of(g);
     if (G.device != s->device)
         return fail(COS_EINVAL, "cos_server_add_graph: graph lives on another device");
+    if (G.kind != FK_RATIONAL)
+        return fail(COS_EINVAL, "cos_server_add_graph: graphs with lookup factors are evaluated with cos_evaluate");
     std::lock_guard<std::mutex> lk(s->mu);
     s->graphs.push_back(&G);
     *gid = static_cast<int32_t>(s->graphs.size() - 1);

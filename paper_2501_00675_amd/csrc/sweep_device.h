@@ -109,6 +109,26 @@ struct LaneSamples32 {
     }
 };
 
+// A lane's K samples for lookup factors: pointers to the samples' entries in
+// table row 0 (rows [slot][sample], ld apart).  Samples at or beyond S
+// (padding) read sample S-1's entries, so every read stays inside the table;
+// their results are never returned.
+template <int K>
+struct LaneTable {
+    const double *p[K];
+    int64_t ld;
+    __device__ __forceinline__ void load(const double *__restrict__ x, int64_t S, int64_t xs, int64_t tbase,
+                                         int lane) {
+        ld = xs;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            p[m] = x + min(tbase + lane + kWave * m, S - 1);
+    }
+    __device__ __forceinline__ double entry(int32_t slot, int m) const {
+        return p[m][static_cast<int64_t>(slot) * ld];
+    }
+};
+
 template <int K>
 __device__ __forceinline__ double factor(const EdgeRec &e, const LaneSamples<K> &xs, int m) {
     return edge_factor64(e, xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]);
@@ -118,21 +138,47 @@ __device__ __forceinline__ float factor(const EdgeRec32 &e, const LaneSamples32<
     return edge_factor32(e, xs.x0[m], xs.x1[m], xs.x2[m]);
 }
 
-// Record and sample types of the interior levels of a sweep with values of type T.
-template <typename T>
+// Edge factor in the value type T: rational factors by their own formula in T;
+// lookup factors as coef * T_s[slot], in binary64, or in binary32 from the
+// binary32 constant and the table entry rounded once.
+template <typename T, typename Rec, typename Smp>
+__device__ __forceinline__ T edge_w(const Rec &r, const Smp &xs, int m) {
+    if constexpr (std::is_same_v<Rec, EdgeRecL>) {
+        const double t = xs.entry(r.slot, m);
+        if constexpr (sizeof(T) == sizeof(double))
+            return r.coef * t;
+        else
+            return r.coef32 * static_cast<float>(t);
+    } else {
+        return factor(r, xs, m);
+    }
+}
+
+// Record and per-lane sample types of the interior levels of a sweep with
+// values of type T and factor kind KIND ...
+template <typename T, int KIND>
 struct SweepPath;
 template <>
-struct SweepPath<double> {
+struct SweepPath<double, FK_RATIONAL> {
     using Rec = EdgeRec;
     template <int K>
     using Samples = LaneSamples<K>;
 };
 template <>
-struct SweepPath<float> {
+struct SweepPath<float, FK_RATIONAL> {
     using Rec = EdgeRec32;
     template <int K>
     using Samples = LaneSamples32<K>;
 };
+template <typename T>
+struct SweepPath<T, FK_LOOKUP> {
+    using Rec = EdgeRecL;
+    template <int K>
+    using Samples = LaneTable<K>;
+};
+// ... and of the final node, whose factors are binary64 at every precision.
+template <int KIND>
+using FinalPath = SweepPath<double, KIND>;
 
 // One wave computes destination rows [jbeg, jend) of a level for the tile at
 // tbase (64*K samples).  The rows' edges form one contiguous stream, walked in
@@ -146,14 +192,14 @@ struct SweepPath<float> {
 //            stored value is its sum times 2^-esh[m] (exact), and lmax[m]
 //            collects the largest |stored value| bit pattern of the lane.
 // Source rows are reached by 32-bit byte offsets (level buffers < 2 GiB).
-template <typename T, int K, bool FROM_ROOT, bool RESCALE>
+template <typename T, int K, bool FROM_ROOT, bool RESCALE, int KIND>
 __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_ptr,
-                                                const typename SweepPath<T>::Rec *edges, int jbeg, int jend,
+                                                const typename SweepPath<T, KIND>::Rec *edges, int jbeg, int jend,
                                                 const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
                                                 int64_t tbase, int lane,
-                                                const typename SweepPath<T>::template Samples<K> &xs,
+                                                const typename SweepPath<T, KIND>::template Samples<K> &xs,
                                                 const int (&esh)[K], uint32_t (&lmax)[K]) {
-    using Rec = typename SweepPath<T>::Rec;
+    using Rec = typename SweepPath<T, KIND>::Rec;
     if (jbeg >= jend)
         return;
     T *const out_base = cur + tbase + lane;
@@ -209,7 +255,7 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
         for (int u = 0; u < C; ++u)
 #pragma unroll
             for (int m = 0; m < K; ++m)
-                w[u][m] = factor(r[u], xs, m);
+                w[u][m] = edge_w<T>(r[u], xs, m);
 #pragma unroll
         for (int u = 0; u < C; ++u) {
             if (decltype(full)::value || u < n) {
@@ -261,14 +307,14 @@ __device__ __forceinline__ void fold_max(uint32_t *red /* LDS [NW][64K] */, cons
 // sequentially in canonical order (one quarter of a final-node chunk).  The
 // source value of edge e comes from src_value(rec, m) (level buffer or LDS).
 // Full chunks accumulate unconditionally, a tail its first n edges only.
-template <int K, bool TOGETHER, typename SrcValue>
-__device__ __forceinline__ void final_sum(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
-                                          const LaneSamples<K> &xs, SrcValue src_value, double (&acc)[K]) {
+template <int K, bool TOGETHER, typename Rec, typename Smp, typename SrcValue>
+__device__ __forceinline__ void final_sum(const Rec *__restrict__ edges, int e_lo, int e_hi, const Smp &xs,
+                                          SrcValue src_value, double (&acc)[K]) {
 #pragma unroll
     for (int m = 0; m < K; ++m)
         acc[m] = 0.0;
     auto chunk = [&](auto full, int e, int n) {
-        EdgeRec r[kChunk];
+        Rec r[kChunk];
         load_chunk<kChunk, TOGETHER>(edges + e, r);
         double v[kChunk][K];
 #pragma unroll
@@ -281,7 +327,7 @@ __device__ __forceinline__ void final_sum(const EdgeRec *__restrict__ edges, int
         for (int u = 0; u < kChunk; ++u)
 #pragma unroll
             for (int m = 0; m < K; ++m)
-                w[u][m] = factor(r[u], xs, m);
+                w[u][m] = edge_w<double>(r[u], xs, m);
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
             if (decltype(full)::value || u < n)
@@ -298,14 +344,15 @@ __device__ __forceinline__ void final_sum(const EdgeRec *__restrict__ edges, int
 
 // final_sum with the level L-1 values in a level buffer (streamed kernels; the
 // records are fetched together, ahead of the vector loads).
-template <typename TV, int K, bool FROM_ROOT>
-__device__ __forceinline__ void final_quarter(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
-                                              const TV *__restrict__ prev, int64_t ld, int64_t tbase, int lane,
-                                              const LaneSamples<K> &xs, double (&acc)[K]) {
+template <typename TV, int K, bool FROM_ROOT, int KIND>
+__device__ __forceinline__ void final_quarter(const typename FinalPath<KIND>::Rec *__restrict__ edges, int e_lo,
+                                              int e_hi, const TV *__restrict__ prev, int64_t ld, int64_t tbase,
+                                              int lane, const typename FinalPath<KIND>::template Samples<K> &xs,
+                                              double (&acc)[K]) {
     const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
     const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(TV));
     const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(TV));
-    final_sum<K, true>(edges, e_lo, e_hi, xs, [&](const EdgeRec &r, int m) -> double {
+    final_sum<K, true>(edges, e_lo, e_hi, xs, [&](const auto &r, int m) -> double {
         if constexpr (FROM_ROOT) {
             return 1.0;
         } else {
@@ -338,12 +385,13 @@ __device__ __forceinline__ void final_combine_one(const double *__restrict__ par
 
 // final_sum with the level L-1 values read from LDS ([node][64K]) or, for
 // L = 1, the root's value 1.
-template <typename T, int K, bool FROM_ROOT>
-__device__ __forceinline__ void final_quarter_lds(const EdgeRec *__restrict__ edges, int e_lo, int e_hi,
-                                                  const T *vals, int lane, const LaneSamples<K> &xs,
+template <typename T, int K, bool FROM_ROOT, int KIND>
+__device__ __forceinline__ void final_quarter_lds(const typename FinalPath<KIND>::Rec *__restrict__ edges, int e_lo,
+                                                  int e_hi, const T *vals, int lane,
+                                                  const typename FinalPath<KIND>::template Samples<K> &xs,
                                                   double (&acc)[K]) {
     constexpr int kTile = kWave * K;
-    final_sum<K, false>(edges, e_lo, e_hi, xs, [&](const EdgeRec &r, int m) -> double {
+    final_sum<K, false>(edges, e_lo, e_hi, xs, [&](const auto &r, int m) -> double {
         if constexpr (FROM_ROOT)
             return 1.0;
         else
@@ -360,6 +408,7 @@ struct FusedGraph {
     const int32_t *row_ptr;
     const EdgeRec *edges;      // binary64 records (binary64 levels, final node)
     const EdgeRec32 *edges32;  // binary32 records (binary32 levels)
+    const EdgeRecL *edgesL;    // lookup records (every level)
     const LevelDev *levels;
     int32_t L;
     const double *x;
@@ -372,11 +421,12 @@ struct FusedGraph {
 // sums of each row (scaled by 2^-esh when RESCALE) into acc, the largest
 // |stored value| bit pattern into lmax.  rpl: lane i (i <= nb) holds the start
 // of row jb + i.  FROM_ROOT: level 1, whose only source is the root (value 1).
-template <typename T, int K, int RMAX, bool FROM_ROOT, bool RESCALE>
-__device__ __forceinline__ void fused_rows(const typename SweepPath<T>::Rec *edges, const T *vals, int nb, int rpl,
-                                           int lane, const typename SweepPath<T>::template Samples<K> &xs,
+template <typename T, int K, int RMAX, bool FROM_ROOT, bool RESCALE, int KIND>
+__device__ __forceinline__ void fused_rows(const typename SweepPath<T, KIND>::Rec *edges, const T *vals, int nb,
+                                           int rpl, int lane,
+                                           const typename SweepPath<T, KIND>::template Samples<K> &xs,
                                            const int (&esh)[K], T (&acc)[RMAX][K], uint32_t (&lmax)[K]) {
-    using Rec = typename SweepPath<T>::Rec;
+    using Rec = typename SweepPath<T, KIND>::Rec;
     constexpr int kTile = kWave * K;
 #pragma unroll
     for (int m = 0; m < K; ++m)
@@ -406,7 +456,7 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T>::Rec *edg
                 for (int u = 0; u < kChunk; ++u)
 #pragma unroll
                     for (int m = 0; m < K; ++m)
-                        w[u][m] = factor(rr[u], xs, m);
+                        w[u][m] = edge_w<T>(rr[u], xs, m);
 #pragma unroll
                 for (int u = 0; u < kChunk; ++u)
                     if (decltype(full)::value || u < n)
@@ -435,14 +485,16 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T>::Rec *edg
 // [w*RMAX, (w+1)*RMAX).  red: [16][64K] uint32 (RESCALE only); part:
 // [quarters][64K] binary64.  The final node is reduced in quarters of 64 edges
 // combined exactly as final_partial / final_combine do.
-template <typename T, int K, int RMAX, bool RESCALE>
+template <typename T, int K, int RMAX, bool RESCALE, int KIND>
 __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T *vals, uint32_t *red, double *part,
                                            int wave, int lane) {
     constexpr int kTile = kWave * K;
-    typename SweepPath<T>::template Samples<K> xs;
+    typename SweepPath<T, KIND>::template Samples<K> xs;
     xs.load(G.x, G.S, G.S, tbase, lane);
-    const typename SweepPath<T>::Rec *edges;
-    if constexpr (sizeof(T) == sizeof(double))
+    const typename SweepPath<T, KIND>::Rec *edges;
+    if constexpr (KIND == FK_LOOKUP)
+        edges = G.edgesL;
+    else if constexpr (sizeof(T) == sizeof(double))
         edges = G.edges;
     else
         edges = G.edges32;
@@ -462,9 +514,9 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
         T acc[RMAX][K];
         uint32_t lmax[K];
         if (l == 1)
-            fused_rows<T, K, RMAX, true, RESCALE>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+            fused_rows<T, K, RMAX, true, RESCALE, KIND>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
         else
-            fused_rows<T, K, RMAX, false, RESCALE>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+            fused_rows<T, K, RMAX, false, RESCALE, KIND>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
         __syncthreads();  // every wave has finished reading level l-1
 #pragma unroll
         for (int r = 0; r < RMAX; ++r)
@@ -496,19 +548,24 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
     // quarter p holds edges [64p, 64p + 64) of the last level
     const LevelDev lf = load_level(G.levels, G.L - 1);
     const int nq = (lf.n_edges + kQuarter - 1) / kQuarter;
-    LaneSamples<K> xd;
-    if constexpr (sizeof(T) == sizeof(double))
+    typename FinalPath<KIND>::template Samples<K> xd;
+    if constexpr (KIND == FK_LOOKUP || sizeof(T) == sizeof(double))
         xd = xs;
     else if (wave < nq)
         xd.load(G.x, G.S, G.S, tbase, lane);
+    const typename FinalPath<KIND>::Rec *fedges;
+    if constexpr (KIND == FK_LOOKUP)
+        fedges = G.edgesL + lf.e_begin;
+    else
+        fedges = G.edges + lf.e_begin;
     for (int p = wave; p < nq; p += kFusedWaves) {
         double acc[K];
         const int e_lo = p * kQuarter;
         const int e_hi = min(e_lo + kQuarter, lf.n_edges);
         if (G.L == 1)
-            final_quarter_lds<T, K, true>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xd, acc);
+            final_quarter_lds<T, K, true, KIND>(fedges, e_lo, e_hi, vals, lane, xd, acc);
         else
-            final_quarter_lds<T, K, false>(G.edges + lf.e_begin, e_lo, e_hi, vals, lane, xd, acc);
+            final_quarter_lds<T, K, false, KIND>(fedges, e_lo, e_hi, vals, lane, xd, acc);
 #pragma unroll
         for (int m = 0; m < K; ++m)
             part[p * kTile + lane + kWave * m] = acc[m];

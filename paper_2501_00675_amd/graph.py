@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import KINDS, LIB, PATHS, PRECISIONS, GraphInfo, check
+from ._lib import FACTOR_KINDS, KINDS, LIB, PATHS, PRECISIONS, GraphInfo, check
 
 
 def _c(a, dtype):
@@ -20,9 +20,14 @@ def _c(a, dtype):
 
 
 class Graph:
-    """A leveled DAG held on the current HIP device (cos_create_graph)."""
+    """A leveled DAG held on the current HIP device.
 
-    def __init__(self, L, widths, edges_per_level, src, dst, a, b, k):
+    Rational factors (cos_create_graph): pass a, b, k.  Lookup factors
+    (cos_create_graph_lookup): pass slot, coef and n_slots instead.
+    """
+
+    def __init__(self, L, widths, edges_per_level, src, dst, a=None, b=None, k=None, *, slot=None, coef=None,
+                 n_slots=None):
         keep = []
 
         def ptr(v, dt):
@@ -31,15 +36,24 @@ class Graph:
             return p
 
         h = ctypes.c_void_p()
-        st = LIB.cos_create_graph(int(L), ptr(widths, np.int64), ptr(edges_per_level, np.int64),
-                                  ptr(src, np.int32), ptr(dst, np.int32), ptr(a, np.float64),
-                                  ptr(b, np.float64), ptr(np.reshape(k, -1), np.float64), ctypes.byref(h))
-        check(st, "cos_create_graph")
+        if slot is not None:
+            st = LIB.cos_create_graph_lookup(int(L), ptr(widths, np.int64), ptr(edges_per_level, np.int64),
+                                             ptr(src, np.int32), ptr(dst, np.int32), ptr(slot, np.int32),
+                                             ptr(coef, np.float64), int(n_slots), ctypes.byref(h))
+            check(st, "cos_create_graph_lookup")
+        else:
+            st = LIB.cos_create_graph(int(L), ptr(widths, np.int64), ptr(edges_per_level, np.int64),
+                                      ptr(src, np.int32), ptr(dst, np.int32), ptr(a, np.float64),
+                                      ptr(b, np.float64), ptr(np.reshape(k, -1), np.float64), ctypes.byref(h))
+            check(st, "cos_create_graph")
         self._h = h
 
     @classmethod
     def from_leveled(cls, g) -> "Graph":
-        """From any object with L, widths, epl, src, dst, a, b, k (e.g. workloads.LeveledGraph)."""
+        """From any object with L, widths, epl, src, dst and either a, b, k or slot, coef, n_slots
+        (e.g. workloads.LeveledGraph)."""
+        if getattr(g, "slot", None) is not None:
+            return cls(g.L, g.widths, g.epl, g.src, g.dst, slot=g.slot, coef=g.coef, n_slots=g.n_slots)
         return cls(g.L, g.widths, g.epl, g.src, g.dst, g.a, g.b, g.k)
 
     @property
@@ -51,7 +65,16 @@ class Graph:
     def info(self) -> dict:
         gi = GraphInfo()
         check(LIB.cos_graph_get_info(self.handle, ctypes.byref(gi)), "cos_graph_get_info")
-        return {f: getattr(gi, f) for f, _ in GraphInfo._fields_}
+        d = {f: getattr(gi, f) for f, _ in GraphInfo._fields_}
+        d["kind"] = FACTOR_KINDS[d["factor_kind"]]
+        return d
+
+    @property
+    def n_inputs(self) -> int:
+        """Rows of the per-sample input: 3 coordinates, or the table entries of a lookup graph."""
+        if getattr(self, "_n_inputs", None) is None:
+            self._n_inputs = self.info()["n_inputs"]
+        return self._n_inputs
 
     def set_path(self, path: str = "auto") -> "Graph":
         """Kernel plan for later evaluations: 'auto', 'streamed' or 'fused' (cos_graph_set_path)."""
@@ -59,7 +82,15 @@ class Graph:
         return self
 
     def export(self) -> dict:
-        E = self.info()["n_edges"]
+        info = self.info()
+        E = info["n_edges"]
+        if info["kind"] == "lookup":
+            out = dict(src=np.empty(E, np.int32), dst=np.empty(E, np.int32), slot=np.empty(E, np.int32),
+                       coef=np.empty(E))
+            check(LIB.cos_graph_export_lookup(self.handle, *[out[n].ctypes.data_as(ctypes.c_void_p)
+                                                             for n in ("src", "dst", "slot", "coef")]),
+                  "cos_graph_export_lookup")
+            return out
         out = dict(src=np.empty(E, np.int32), dst=np.empty(E, np.int32), a=np.empty(E), b=np.empty(E),
                    k=np.empty((E, 3)))
         check(LIB.cos_graph_export(self.handle, *[out[n].ctypes.data_as(ctypes.c_void_p)
@@ -75,10 +106,15 @@ class Graph:
     def evaluate(self, x: torch.Tensor, precision: str = "fp64", out: torch.Tensor | None = None,
                  out_exp: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
                  stream: torch.cuda.Stream | None = None) -> torch.Tensor:
-        """Final-node value for the samples x (float64[3, S] on the device), queued on `stream`."""
+        """Final-node value per sample, queued on `stream`.
+
+        x: float64[R, S] on the device, R = 3 (coordinates) for rational factors or
+        n_slots (each sample's table) for lookup factors.
+        """
+        rows = self.n_inputs
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 2
-                and x.shape[0] == 3 and x.is_contiguous()):
-            raise ValueError("x must be a contiguous float64 CUDA tensor of shape [3, S]")
+                and x.shape[0] == rows and x.is_contiguous()):
+            raise ValueError(f"x must be a contiguous float64 CUDA tensor of shape [{rows}, S]")
         S = x.shape[1]
         if out is None:
             out = torch.empty(S, dtype=torch.float64, device=x.device)

@@ -38,7 +38,7 @@ def test_build_id_matches_sources_and_abi_version():
     from paper_2501_00675_amd import _build
 
     assert P.LIB.cos_build_id().decode() == _build.source_hash()
-    assert P.LIB.cos_abi_version() == 1
+    assert P.LIB.cos_abi_version() == 2
 
 
 def _create(g, **over):
@@ -84,6 +84,30 @@ def test_create_rejects_invalid_input(case):
     st, msg, h = _create(g, **over)
     assert st == -1, (st, msg)
     assert msg and not h.value
+
+
+@pytest.mark.parametrize("case", ["slot_high", "slot_negative", "nan_coef", "no_slots", "null_slot"])
+def test_create_lookup_rejects_invalid_input(case):
+    import paper_2501_00675_amd._lib as L
+
+    g, _ = make_config("tiny", S=1, factor="lookup")
+    slot, coef, n_slots = g.slot.copy(), g.coef.copy(), g.n_slots
+    if case == "slot_high":
+        slot[4] = n_slots
+    elif case == "slot_negative":
+        slot[0] = -1
+    elif case == "nan_coef":
+        coef[2] = np.nan
+    elif case == "no_slots":
+        n_slots = 0
+    arrs = [np.asarray(g.widths, np.int64), np.asarray(g.epl, np.int64), np.asarray(g.src, np.int32),
+            np.asarray(g.dst, np.int32), slot, coef]
+    ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+    if case == "null_slot":
+        ptrs[4] = None
+    h = ctypes.c_void_p()
+    st = L.LIB.cos_create_graph_lookup(g.L, *ptrs, n_slots, ctypes.byref(h))
+    assert st == -1 and L.LIB.cos_last_error().decode() and not h.value
 
 
 def test_evaluate_rejects_null_and_bad_args():
