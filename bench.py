@@ -7,7 +7,10 @@ the rescaled FP32 path the exponent bookkeeping) of the workload's graph for
 all S samples, with the graph, the samples and the workspace already resident
 in HBM.  Prints one JSON line.  The CPU-baseline leg times the plain FP64
 oracle on the host cores; its outputs are also the reference for the reported
-error of the GPU results.  The serving leg ("serving" in the JSON) replays the
+error of the GPU results (every oracle call of this script happens in that leg,
+on outputs the other legs sampled).  The lookup leg ("lookup") times the same
+workload with the paper's own edge factor, a per-sample table entry times a
+sign.  The serving leg ("serving" in the JSON) replays the
 serving request stream through the continuous-batching server and through
 one-at-a-time evaluation, and reports p50/p99 request latency beside
 throughput.
@@ -46,20 +49,38 @@ WORKLOAD_TEXT = {
 }
 
 
+def record_bytes(g, precision: str) -> int:
+    """Record fields a level needs per edge: rational binary64 src (4 B) + c0, cb, g0, g1, g2, a (6 x 8 B);
+    rational binary32 src + a, b, k0, k1, k2 (5 x 4 B); lookup src + slot (2 x 4 B) + the constant
+    (8 B binary64, 4 B binary32)."""
+    if g.kind == "lookup":
+        return 8 + (8 if precision == "fp64" else 4)
+    return 4 + 6 * 8 if precision == "fp64" else 4 + 5 * 4
+
+
+def input_bytes(g, S_pad: int) -> int:
+    """Per-sample inputs read once: 3 coordinates, or the table (n_slots entries), in binary64."""
+    return 8 * g.n_inputs * S_pad
+
+
 def level_bytes(g, S_pad: int, precision: str) -> list:
     """Algorithmic bytes of each interior-level launch: read the previous level's
     rows once, write this level's rows once, read the edge records and row
-    pointers once, read x once (S samples, 3 x float64)."""
+    pointers once, read the per-sample inputs once."""
     B = 8 if precision == "fp64" else 4
-    # record fields a launch needs: binary64 sweeps src (4 B) + c0, cb, g0, g1, g2, a (6 x 8 B);
-    # binary32 sweeps src (4 B) + a, b, k0, k1, k2 (5 x 4 B)
-    rec = 4 + 6 * 8 if precision == "fp64" else 4 + 5 * 4
+    rec = record_bytes(g, precision)
     out = []
     for l in range(1, g.L):
         w_prev = 0 if l == 1 else int(g.widths[l - 1])  # level 1 reads the root's constant 1
         out.append((w_prev + int(g.widths[l])) * S_pad * B + int(g.epl[l - 1]) * rec
-                   + 4 * (int(g.widths[l]) + 1) + 24 * S_pad)
+                   + 4 * (int(g.widths[l]) + 1) + input_bytes(g, S_pad))
     return out
+
+
+def flops_per_edge_sample(g) -> int:
+    """Algorithmic flops per edge-sample: the rational factor and accumulate (13), or the
+    lookup factor's product with the constant and the accumulate (2)."""
+    return 2 if g.kind == "lookup" else FLOPS_PER_EDGE_SAMPLE
 
 
 def cpu_info() -> str:
@@ -155,7 +176,7 @@ def roofline(g, S_pad, precision, kern, steps, workload):
         es_step = float(sum(int(g.epl[l - 1]) for l in range(1, g.L))) * S_pad
         t_step = kern[dom]["total_ms"] / 1000.0 / steps
         hbm = bytes_step / t_step / 1e9
-        alu = es_step * FLOPS_PER_EDGE_SAMPLE / t_step / 1e12
+        alu = es_step * flops_per_edge_sample(g) / t_step / 1e12
         f_h, f_a = hbm / HBM_PEAK_GBS, alu / VALU_PEAK_TFLOPS[precision]
         if f_h >= f_a:
             r = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": f_h}
@@ -167,18 +188,22 @@ def roofline(g, S_pad, precision, kern, steps, workload):
                   "other_term": ({"alu_tflops": alu, "alu_frac": f_a} if r["bound"] == "hbm"
                                  else {"hbm_gbs": hbm, "hbm_frac": f_h})})
     elif dom == "fused":
-        # whole graph per launch with levels in LDS: every edge-sample of every level, 13 flops each
+        # whole graph per launch with levels in LDS: every edge-sample of every level
         es_step = float(g.n_edges) * S_pad
         t_launch = kern[dom]["total_ms"] / 1000.0 / kern[dom]["launches"]
         n_launch = kern[dom]["launches"] / steps
-        alu = es_step / n_launch * FLOPS_PER_EDGE_SAMPLE / t_launch / 1e12
-        # compulsory HBM bytes: x in, out written, edge records read once per 64-sample workgroup
-        hbm_bytes = S_pad * (24 + 8) + g.n_edges * 64 * (S_pad // 64)
+        fl = flops_per_edge_sample(g)
+        alu = es_step / n_launch * fl / t_launch / 1e12
+        # compulsory HBM bytes: per-sample inputs in, out written, edge records once per 64-sample workgroup
+        hbm_bytes = input_bytes(g, S_pad) + 8 * S_pad + g.n_edges * record_bytes(g, precision) * (S_pad // 64)
         r = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
              "frac": alu / VALU_PEAK_TFLOPS[precision], "kernel": "fused_sweep_kernel",
              "avg_launch_us": kern[dom]["avg_us"], "launches_per_step": n_launch,
-             "algorithmic_flops_per_launch": es_step / n_launch * FLOPS_PER_EDGE_SAMPLE,
+             "algorithmic_flops_per_launch": es_step / n_launch * fl,
              "other_term": {"hbm_gbs_compulsory": hbm_bytes / t_launch / 1e9}}
+        if g.kind == "lookup":
+            # the binding stream is the table entry each edge-sample reads (from L1/L2)
+            r["other_term"]["table_gbs_read"] = es_step / n_launch * 8 / t_launch / 1e9
     else:
         r = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "kernel": dom}
     r["traffic"] = profiled_traffic(r.get("kernel"), workload, precision)
@@ -245,6 +270,56 @@ def calibrate_copy(steps: int, nbytes: int = 1 << 30):
     print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": nbytes,
                       "bytes_written_per_launch": nbytes, "ms_per_launch": ms,
                       "copy_GBps": 2 * nbytes / (ms / 1000) / 1e9}), flush=True)
+
+
+FACTOR_TEXT = {"rational": "; w_e = a_e/(1+b_e|x-k_e|^2), x in R^3 per sample",
+               "lookup": "; w_e = c_e*T_s[slot_e], c_e = +-1, T_s ~ U[-1,1]^{n} per sample"}
+
+
+def lookup_leg(P, args):
+    """The same workload with lookup factors (the paper's Green's-function-per-vertex-pair form):
+    FP64 and FP32-rescaled throughput and roofline terms.  Returns the results and the sampled
+    outputs the CPU-baseline leg checks against the oracle."""
+    import torch
+
+    from workloads import make_config
+
+    g, T = make_config(args.workload, factor="lookup")
+    S = T.shape[1]
+    S_pad = (S + 255) // 256 * 256
+    G = P.Graph.from_leveled(g)
+    Td = torch.from_numpy(T).to("cuda:0")
+    idx = np.unique(np.concatenate([[0, S - 1], np.random.default_rng(1).choice(S, min(S, 256) - 2,
+                                                                                 replace=False)]))
+    res = {"workload": WORKLOAD_TEXT[args.workload] + FACTOR_TEXT["lookup"].format(n=g.n_inputs)}
+    check = {"graph": g, "x": np.ascontiguousarray(T[:, idx]), "y": {}, "into": res}
+    for p in ("fp64", "fp32r"):
+        print(f"# lookup {p}", file=sys.stderr, flush=True)
+        ms, kern, out = run_timed(P, G, Td, p, args.steps, args.warmup)
+        res[p] = {"value": g.n_edges * S / (ms / 1000.0), "ms_per_step": ms, "kernels": kern,
+                  "roofline": roofline(g, S_pad, p, kern, args.steps, args.workload + "_lookup")}
+        check["y"][p] = out.cpu().numpy()[idx]
+    return res, [check]
+
+
+def reference_checks(checks):
+    """Part of the CPU-baseline leg: the oracle's values on the sampled outputs of the other legs, and
+    the resulting error statistics (written into each check's result dict)."""
+    import oracle
+
+    for c in checks:
+        V = oracle.sweep(c["graph"], c["x"], "value")
+        Q = oracle.sweep(c["graph"], c["x"], "square")
+        for p, y in c["y"].items():
+            if "requests" in c:  # serving: worst case over the checked requests
+                acc = c["into"].setdefault("accuracy", {"requests_checked": c["requests"],
+                                                        "samples_per_request": "<=128", "scaled_max": {},
+                                                        "pass": True})
+                e = float(oracle.scaled_error(y, V, Q).max())
+                acc["scaled_max"][p] = max(acc["scaled_max"].get(p, 0.0), e)
+                acc["pass"] = bool(acc["pass"] and e <= TOL[p])
+            else:
+                c["into"][p]["accuracy"] = error_stats(y, V, Q, p)
 
 
 SERVING_TEXT = ("serving: 512 resident graphs, L~U{4..20}, interior width log-U[16,2048], in-degree U{2..8}; "
@@ -357,28 +432,16 @@ def serving_leg(P, args):
     # results of the last trace: batched FP64 bit-identical to one-at-a-time FP64 for every request
     same = torch.eq(outs["fp64"].view(torch.int64), outs["single"].view(torch.int64))
     res["fp64_batched_bit_identical_to_single"] = bool(same.all().item())
-    # oracle check of a seeded subset of requests (64 requests, up to 128 samples each)
-    if not args.no_cpu_baseline:
-        import oracle
-
-        pick = np.random.default_rng(5).choice(len(reqs), 64, replace=False)
-        worst = {"fp64": 0.0, "fp32r": 0.0}
-        ok = True
-        for i in pick:
-            r = reqs[i]
-            idx = np.unique(np.random.default_rng(int(i)).choice(r["S"], min(r["S"], 128), replace=False))
-            xr = np.ascontiguousarray(r["x"][:, idx])
-            V = oracle.sweep(graphs[r["graph"]], xr, "value")
-            Q = oracle.sweep(graphs[r["graph"]], xr, "square")
-            for p in worst:
-                y = out_view(p, i).cpu().numpy()[idx]
-                e = float(oracle.scaled_error(y, V, Q).max())
-                worst[p] = max(worst[p], e)
-                ok &= e <= TOL[p]
-        res["accuracy"] = {"requests_checked": 64, "samples_per_request": "<=128", "scaled_max": worst,
-                           "pass": bool(ok)}
+    # sampled outputs of a seeded subset of requests (64 requests, up to 128 samples each), checked
+    # against the oracle by the CPU-baseline leg
+    checks = []
+    for i in np.random.default_rng(5).choice(len(reqs), 64, replace=False):
+        r = reqs[i]
+        idx = np.unique(np.random.default_rng(int(i)).choice(r["S"], min(r["S"], 128), replace=False))
+        checks.append({"graph": graphs[r["graph"]], "x": np.ascontiguousarray(r["x"][:, idx]), "requests": 64,
+                       "into": res, "y": {p: out_view(p, i).cpu().numpy()[idx] for p in ("fp64", "fp32r")}})
     srv.close()
-    return res
+    return res, checks
 
 
 def main():
@@ -393,6 +456,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain 1 GiB device copy (reference for HBM counters and bandwidth)")
+    ap.add_argument("--factor", default="rational", choices=["rational", "lookup"],
+                    help="edge-factor kind of the timed workload")
+    ap.add_argument("--no-lookup", action="store_true", help="skip the lookup-factor block of the default run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--serve-slots", type=int, default=256)
@@ -414,9 +480,12 @@ def main():
     from workloads import make_config
 
     if args.serving_only:
-        print(json.dumps({"serving": serving_leg(P, args)}), flush=True)
+        res, checks = serving_leg(P, args)
+        if not args.no_cpu_baseline:
+            reference_checks(checks)
+        print(json.dumps({"serving": res}), flush=True)
         return
-    g, x = make_config(args.workload)
+    g, x = make_config(args.workload, factor=args.factor)
     S = x.shape[1]
     E = g.n_edges
     G = P.Graph.from_leveled(g)
@@ -432,8 +501,9 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[args.precision], "data": "synthetic (seeded generator; stands in for the paper's CoS graphs)",
-        "config": {"workload": WORKLOAD_TEXT[args.workload], "L": g.L, "edges": E, "nodes": g.n_nodes, "S": S,
-                   "precision": args.precision, "seed": g.meta.get("seed")},
+        "config": {"workload": WORKLOAD_TEXT[args.workload] + FACTOR_TEXT[args.factor].format(n=g.n_inputs),
+                   "L": g.L, "edges": E, "nodes": g.n_nodes, "S": S, "precision": args.precision,
+                   "factor": args.factor, "seed": g.meta.get("seed")},
         "kernels": kern,
         "roofline": roofline(g, S_pad, args.precision, kern, args.steps, args.workload),
     }
@@ -443,6 +513,13 @@ def main():
         msv, kv, outv = run_timed(P, G, xd, pv, args.steps, args.warmup)
         variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "kernels": kv,
                         "roofline": roofline(g, S_pad, pv, kv, args.steps, args.workload), "_y": outv.cpu().numpy()}
+    checks = []
+    if args.factor == "rational" and not args.no_lookup:
+        result["lookup"], c = lookup_leg(P, args)
+        checks += c
+    if not args.no_serving:
+        result["serving"], c = serving_leg(P, args)
+        checks += c
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         idx = np.unique(np.concatenate([[0, S - 1], np.random.default_rng(0).choice(S, min(S, 1024) - 2,
@@ -452,13 +529,12 @@ def main():
         result["accuracy"] = error_stats(y[idx], V, Q, args.precision)
         for pv, d in variants.items():
             d["accuracy"] = error_stats(d["_y"][idx], V, Q, pv)
+        reference_checks(checks)
     else:
         result["cpu_baseline"] = None
     for d in variants.values():
         d.pop("_y", None)
     result["variants"] = variants
-    if not args.no_serving:
-        result["serving"] = serving_leg(P, args)
     print(json.dumps(result), flush=True)
 
 
