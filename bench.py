@@ -35,12 +35,15 @@ sys.path.insert(0, ROOT)
 METRIC = "edge-sample updates/s (FP64 vs FP32) at stated rel err; p50/p99 request latency"
 UNIT = "edge-sample updates/s"
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32r": 157.3, "fp32": 157.3}
+VALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32r": 157.3, "fp32": 157.3, "fp16r": 157.3, "bf16r": 157.3}
 # algorithmic flops per edge-sample of the fused factor + accumulate:
 # 3 sub, |.|^2 = 1 mul + 2 fma (5), 1 + b r^2 = fma (2), divide (1), acc fma (2)
 FLOPS_PER_EDGE_SAMPLE = 13
-TOL = {"fp64": 1e-12, "fp32r": 1e-5, "fp32": 1e-5}
-DTYPE = {"fp64": "f64", "fp32r": "f32", "fp32": "f32"}
+# 16-bit storage has no fixed tolerance: its bar is a per-sample bound derived from the
+# arithmetic, checked by the parity tests; the bench reports its errors only
+TOL = {"fp64": 1e-12, "fp32r": 1e-5, "fp32": 1e-5, "fp16r": None, "bf16r": None}
+DTYPE = {"fp64": "f64", "fp32r": "f32", "fp32": "f32", "fp16r": "f32", "bf16r": "f32"}
+VALUE_BYTES = {"fp64": 8, "fp32r": 4, "fp32": 4, "fp16r": 2, "bf16r": 2}
 WORKLOAD_TEXT = {
     "tiny": "tiny: L=4, widths [1,3,4,3,1], in-degree 2, S=1024, x~U[-1,1]^3",
     "mid": "mid: L=12, interior width 256, in-degree 4, S=65536, x~N(0,I3)",
@@ -67,7 +70,7 @@ def level_bytes(g, S_pad: int, precision: str) -> list:
     """Algorithmic bytes of each interior-level launch: read the previous level's
     rows once, write this level's rows once, read the edge records and row
     pointers once, read the per-sample inputs once."""
-    B = 8 if precision == "fp64" else 4
+    B = VALUE_BYTES[precision]
     rec = record_bytes(g, precision)
     out = []
     for l in range(1, g.L):
@@ -130,8 +133,9 @@ def error_stats(y, V, Q, precision):
     with np.errstate(divide="ignore", invalid="ignore"):
         plain = np.abs(y - V) / np.abs(V)
     plain = plain[np.isfinite(plain)]
-    return {"scaled_max": float(scaled.max()), "tol": TOL[precision],
-            "pass": bool(np.all(scaled <= TOL[precision])),
+    tol = TOL[precision]
+    return {"scaled_max": float(scaled.max()), "tol": tol,
+            "pass": bool(np.all(scaled <= tol)) if tol is not None else None,
             "plain_rel_p50": float(np.percentile(plain, 50)), "plain_rel_p99": float(np.percentile(plain, 99)),
             "plain_rel_max": float(plain.max()), "samples_checked": int(len(y)),
             "definition": "|y-r|/max(|r|,sqrt(Q)), r = FP64 oracle, Q = sum over paths of prod w^2"}
@@ -450,8 +454,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mid", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r", "fp32"])
-    ap.add_argument("--variants", default="fp32r", help="comma list of extra precisions to time ('' for none)")
+    ap.add_argument("--precision", default="fp64", choices=sorted(TOL))
+    ap.add_argument("--variants", default="fp32r,fp16r,bf16r",
+                    help="comma list of extra precisions to time ('' for none; fp16r is skipped for lookup factors)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -508,7 +513,8 @@ def main():
         "roofline": roofline(g, S_pad, args.precision, kern, args.steps, args.workload),
     }
     variants = {}
-    for pv in [v for v in args.variants.split(",") if v and v != args.precision]:
+    for pv in [v for v in args.variants.split(",") if v and v != args.precision
+               and not (v == "fp16r" and g.kind == "lookup")]:
         print(f"# variant {pv}", file=sys.stderr, flush=True)
         msv, kv, outv = run_timed(P, G, xd, pv, args.steps, args.warmup)
         variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "kernels": kv,

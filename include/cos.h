@@ -63,7 +63,21 @@ typedef enum cos_precision {
        "Numerical stability"); the rescale is this library's addition. */
     COS_FP32_RESCALED = 1,
     /* as COS_FP32_RESCALED without the rescale (the paper's plain FP32) */
-    COS_FP32 = 2
+    COS_FP32 = 2,
+    /* as COS_FP32_RESCALED, with the interior level values stored in IEEE
+       binary16 (half the level bytes; arithmetic stays binary32).  The
+       per-(level, sample) shift also carries a per-level headroom 2^h computed
+       at graph creation from the largest row sum of |a_e|, so that no stored
+       value can exceed the binary16 range.  Rational factors only (lookup
+       factors have no such bound: COS_EINVAL), streamed plan only.  Storage
+       rounding makes it less accurate than binary32 (relative rounding 2^-11
+       per stored level; the paper's Sec. IV suggests trading precision for
+       speed in this direction). */
+    COS_FP16_RESCALED = 3,
+    /* the same with bfloat16 storage (relative rounding 2^-8 per stored
+       level, binary32's exponent range, no headroom needed); both factor
+       kinds, streamed plan only. */
+    COS_BF16_RESCALED = 4
 } cos_precision;
 
 typedef struct cos_graph cos_graph;
@@ -198,7 +212,8 @@ cos_status cos_evaluate_workspace_size(const cos_graph *g, int64_t S, cos_precis
  *                rational factors (the sample's coordinates), R = n_slots for
  *                lookup factors (the sample's table T_s).
  *   S            >= 0 (0: nothing is queued).
- *   p            COS_FP64, COS_FP32_RESCALED or COS_FP32.
+ *   p            a cos_precision.  COS_FP16_RESCALED needs rational
+ *                factors whose largest level row sum of |a_e| is below 2^110.
  *   out_dev      device float64[S].  Without out_exp_dev: the value V(x_s).
  *   out_exp_dev  device int32[S] or NULL.  When given, the result is returned
  *                as out_dev[s] * 2^out_exp_dev[s] (for values whose magnitude
@@ -276,7 +291,7 @@ cos_status cos_server_add_graph(cos_server *srv, const cos_graph *g, int32_t *gi
  * Queue a request: x_dev device float64[3][S], out_dev device float64[S],
  * out_exp_dev device int32[S] or NULL (as for cos_evaluate).  The caller keeps
  * them alive until the request ends (poll/wait return a final status).  Never
- * blocks.  Errors: COS_EINVAL (unknown gid, S < 1, bad precision, S too large
+ * blocks.  Errors: COS_EINVAL (unknown gid, S < 1, bad or 16-bit precision, S too large
  * for one sweep), COS_ENOMEM (the request's workspace exceeds the whole
  * budget, so it could never be admitted).
  */

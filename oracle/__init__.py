@@ -54,6 +54,10 @@ def _bind(lib):
     lib.oracle_check_lookup.argtypes = [i32, p, p, p, p, p, p, i32]
     lib.oracle_sweep_lookup.restype = ctypes.c_int
     lib.oracle_sweep_lookup.argtypes = [i32, p, p, p, p, p, p, i32, p, i64, i32, i32, p, p]
+    lib.oracle_sweep_nodes.restype = ctypes.c_int
+    lib.oracle_sweep_nodes.argtypes = [i32, p, p, p, p, p, p, p, p, i64, i32, i32, p, p]
+    lib.oracle_sweep_lookup_nodes.restype = ctypes.c_int
+    lib.oracle_sweep_lookup_nodes.argtypes = [i32, p, p, p, p, p, p, i32, p, i64, i32, i32, p, p]
     return lib
 
 
@@ -143,6 +147,31 @@ def sweep(g, x, mode: str = "value", threads: int = 0, lib=None, return_threads:
     if rc != 0:
         raise ValueError(f"oracle sweep failed with code {rc}")
     return (out, used.value) if return_threads else out
+
+
+def node_values(g, x, mode: str = "value", threads: int = 0, lib=None):
+    """Every node's value after the sweep: float64[n_nodes, S] (node n holds the
+    sum over root-to-n paths of the product of the factors, or of their |w| or
+    w^2 in the norm modes).  Row n_nodes - 1 is what sweep() returns."""
+    lib = lib or load()
+    A = _arrays(g)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    rows = int(g.n_slots) if _is_lookup(g) else 3
+    if x.ndim != 2 or x.shape[0] != rows:
+        raise ValueError(f"x must be float64[{rows}, S]")
+    S = x.shape[1]
+    out = np.empty(S, dtype=np.float64)
+    nodes = np.empty((int(np.sum(g.widths)), S), dtype=np.float64)
+    if _is_lookup(g):
+        rc = lib.oracle_sweep_lookup_nodes(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "slot", "coef")],
+                                           int(g.n_slots), _ptr(x), S, MODES[mode], int(threads), _ptr(out),
+                                           _ptr(nodes))
+    else:
+        rc = lib.oracle_sweep_nodes(g.L, *[_ptr(A[n]) for n in ("widths", "epl", "src", "dst", "a", "b", "k")],
+                                    _ptr(x), S, MODES[mode], int(threads), _ptr(out), _ptr(nodes))
+    if rc != 0:
+        raise ValueError(f"oracle sweep failed with code {rc}")
+    return nodes
 
 
 def evaluate(g, x, threads: int = 0, lib=None):

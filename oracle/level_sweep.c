@@ -31,6 +31,9 @@
  * mode 1: A(x) = sum_paths prod |w_e(x)|   (1-norm of the path terms)
  * mode 2: Q(x) = sum_paths prod w_e(x)^2   (squared 2-norm of the path terms)
  *
+ * The *_nodes entry points also return the value every node holds after the
+ * sweep (the sum over root-to-node paths), for every sample.
+ *
  * Parity pins: brute-force exact path sums, closed forms, transpose invariance
  * and exact power-of-two scaling (see the oracle tests).
  */
@@ -141,11 +144,13 @@ static double edge_factor(double a, double b, const double *k, double x0, double
  * The sweep for either kind.  kind 0: x is float64[3][S] (coordinates), the
  * factor rational; kind 1: x is float64[n_slots][S] (each sample's table
  * T_s[slot] = x[slot * S + s]), the factor c_e * T_s[slot_e].  out: float64[S].
+ * nodes (nullable): float64[n_nodes][S], every node's value.
  */
 static int sweep(int32_t kind, int32_t L, const int64_t *widths, const int64_t *epl,
                  const int32_t *src, const int32_t *dst, const double *a, const double *b,
                  const double *k, const int32_t *slot, const double *coef, const double *x,
-                 int64_t S, int32_t mode, int32_t nthreads, double *out, int32_t *threads_used)
+                 int64_t S, int32_t mode, int32_t nthreads, double *out, double *nodes,
+                 int32_t *threads_used)
 {
     if (S < 0 || mode < 0 || mode > 2)
         return ORACLE_EINVAL;
@@ -225,6 +230,10 @@ static int sweep(int32_t kind, int32_t L, const int64_t *widths, const int64_t *
             }
             for (int64_t j = 0; j < nb; ++j)
                 out[s0 + j] = value[final_node * SAMPLE_BLOCK + j];
+            if (nodes)
+                for (int64_t n = 0; n < n_nodes; ++n)
+                    for (int64_t j = 0; j < nb; ++j)
+                        nodes[n * S + s0 + j] = value[n * SAMPLE_BLOCK + j];
         }
         free(value);
     }
@@ -248,7 +257,20 @@ int oracle_sweep(int32_t L, const int64_t *widths, const int64_t *epl,
     int rc = oracle_check(L, widths, epl, src, dst, a, b, k);
     if (rc != ORACLE_OK)
         return rc;
-    return sweep(0, L, widths, epl, src, dst, a, b, k, NULL, NULL, x, S, mode, nthreads, out, threads_used);
+    return sweep(0, L, widths, epl, src, dst, a, b, k, NULL, NULL, x, S, mode, nthreads, out, NULL,
+                 threads_used);
+}
+
+/* oracle_sweep that also fills nodes: float64[n_nodes][S]. */
+int oracle_sweep_nodes(int32_t L, const int64_t *widths, const int64_t *epl,
+                       const int32_t *src, const int32_t *dst, const double *a,
+                       const double *b, const double *k, const double *x, int64_t S,
+                       int32_t mode, int32_t nthreads, double *out, double *nodes)
+{
+    int rc = oracle_check(L, widths, epl, src, dst, a, b, k);
+    if (rc != ORACLE_OK)
+        return rc;
+    return sweep(0, L, widths, epl, src, dst, a, b, k, NULL, NULL, x, S, mode, nthreads, out, nodes, NULL);
 }
 
 /* Lookup factors.  table: float64[n_slots][S], out: float64[S]. */
@@ -261,5 +283,18 @@ int oracle_sweep_lookup(int32_t L, const int64_t *widths, const int64_t *epl,
     if (rc != ORACLE_OK)
         return rc;
     return sweep(1, L, widths, epl, src, dst, NULL, NULL, NULL, slot, coef, table, S, mode, nthreads, out,
-                 threads_used);
+                 NULL, threads_used);
+}
+
+/* oracle_sweep_lookup that also fills nodes: float64[n_nodes][S]. */
+int oracle_sweep_lookup_nodes(int32_t L, const int64_t *widths, const int64_t *epl,
+                              const int32_t *src, const int32_t *dst, const int32_t *slot,
+                              const double *coef, int32_t n_slots, const double *table, int64_t S,
+                              int32_t mode, int32_t nthreads, double *out, double *nodes)
+{
+    int rc = oracle_check_lookup(L, widths, epl, src, dst, slot, coef, n_slots);
+    if (rc != ORACLE_OK)
+        return rc;
+    return sweep(1, L, widths, epl, src, dst, NULL, NULL, NULL, slot, coef, table, S, mode, nthreads, out,
+                 nodes, NULL);
 }

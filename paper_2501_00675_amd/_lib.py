@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcosdag.s
 COS_OK, COS_EINVAL, COS_ENOMEM, COS_EDEVICE, COS_EAGAIN, COS_ECANCELED = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "COS_OK", -1: "COS_EINVAL", -2: "COS_ENOMEM", -3: "COS_EDEVICE", -4: "COS_EAGAIN",
                 -5: "COS_ECANCELED"}
-PRECISIONS = {"fp64": 0, "fp32r": 1, "fp32": 2}
+PRECISIONS = {"fp64": 0, "fp32r": 1, "fp32": 2, "fp16r": 3, "bf16r": 4}
 KINDS = {"level": 0, "fused": 1, "final_partial": 2, "final_combine": 3, "fill": 4, "serve": 5}
 
 # every symbol include/cos.h declares (checked by the tests)

@@ -89,6 +89,9 @@ struct Graph {
     int64_t n_nodes = 0, n_edges = 0;
     int64_t max_width = 0;            // interior levels 1..L-1
     int64_t max_in_degree = 0;        // interior levels 1..L-1
+    // binary16 storage: headroom exponent h[l] of node level l = 1..L-1
+    // (h[0] unused); empty when the graph's factors have no bound (lookup)
+    std::vector<int32_t> h16;
     // canonical host copy (for export)
     std::vector<int32_t> h_src, h_dst;
     std::vector<double> h_a, h_b, h_k;       // rational factors
@@ -139,6 +142,17 @@ constexpr int kFusedWaves = 16;      // wavefronts per workgroup of the LDS-resi
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// Precisions whose interior levels carry the per-(level, sample) exponent.
+inline bool is_rescaled(cos_precision p) {
+    return p == COS_FP32_RESCALED || p == COS_FP16_RESCALED || p == COS_BF16_RESCALED;
+}
+// Bytes of one stored level value.
+inline size_t value_bytes(cos_precision p) {
+    return p == COS_FP64 ? 8 : (p == COS_FP16_RESCALED || p == COS_BF16_RESCALED) ? 2 : 4;
+}
+// Largest headroom exponent of binary16 storage (row sums of |a| up to 2^110).
+constexpr int32_t kMaxHeadroom16 = 96;
+
 // Workspace layout of one evaluate call.  The streamed plan sweeps the graph
 // once per chunk of S_chunk samples (S_pad = S_chunk rounded to kSamplePad);
 // a chunk's level buffer stays below kMaxLevelBytes so kernels can address
@@ -161,9 +175,11 @@ int64_t max_chunk(const Graph &g, cos_precision p);
 
 // Kernel launchers.  All return hipSuccess or the launch error.  x points at
 // the chunk's first sample; xs is the distance between coordinate rows of x.
+// Rescaled precisions: prev_max / cur_max are the maxbits rows l-1 and l,
+// h_next the headroom exponent folded into cur_max (0 unless binary16).
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur,
                         int64_t ld, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
-                        uint32_t *cur_max, hipStream_t s);
+                        uint32_t *cur_max, int32_t h_next, hipStream_t s);
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld,
                         const double *x, int64_t S, int64_t xs, const uint32_t *maxbits, double *partial,
                         int32_t chunks, double *out, int32_t *out_exp, hipStream_t s);

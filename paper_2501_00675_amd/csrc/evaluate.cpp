@@ -7,7 +7,7 @@
 namespace cosdag {
 
 namespace {
-size_t elem_size(cos_precision p) { return p == COS_FP64 ? sizeof(double) : sizeof(float); }
+size_t elem_size(cos_precision p) { return value_bytes(p); }
 }  // namespace
 
 // Largest chunk (multiple of kSamplePad) whose level buffer stays below
@@ -31,7 +31,7 @@ Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p) {
     };
     w.off_buf0 = take(level_bytes);
     w.off_buf1 = take(level_bytes);
-    w.off_maxbits = p == COS_FP32_RESCALED ? take(static_cast<size_t>(g.L + 1) * w.S_pad * sizeof(uint32_t)) : 0;
+    w.off_maxbits = is_rescaled(p) ? take(static_cast<size_t>(g.L + 1) * w.S_pad * sizeof(uint32_t)) : 0;
     w.final_chunks = final_chunk_count(g.levels.back().n_edges);
     w.off_partial = take(static_cast<size_t>(w.final_chunks) * w.S_pad * sizeof(double));
     w.bytes = std::max<size_t>(off, 256);
@@ -55,23 +55,37 @@ Workspace plan_workspace(const Graph &g, int64_t S, cos_precision p) {
 using namespace cosdag;
 
 namespace {
-bool valid_precision(cos_precision p) { return p == COS_FP64 || p == COS_FP32_RESCALED || p == COS_FP32; }
+bool valid_precision(cos_precision p) {
+    return p == COS_FP64 || p == COS_FP32_RESCALED || p == COS_FP32 || p == COS_FP16_RESCALED ||
+           p == COS_BF16_RESCALED;
+}
+
+// Headroom exponent of node level l under precision p (binary16 only).
+int32_t headroom(const Graph &g, cos_precision p, int l) {
+    return p == COS_FP16_RESCALED ? g.h16[static_cast<size_t>(l)] : 0;
+}
 
 // One streamed sweep of the graph for samples [0, S) of the chunk starting at x.
 hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char *base, const double *x,
                        int64_t S, int64_t xs, double *out, int32_t *out_exp, hipStream_t st) {
     void *bufs[2] = {base + w.off_buf0, base + w.off_buf1};
-    uint32_t *maxbits = p == COS_FP32_RESCALED ? reinterpret_cast<uint32_t *>(base + w.off_maxbits) : nullptr;
+    uint32_t *maxbits = is_rescaled(p) ? reinterpret_cast<uint32_t *>(base + w.off_maxbits) : nullptr;
     double *partial = reinterpret_cast<double *>(base + w.off_partial);
     hipError_t err = hipSuccess;
+    // row 0: the root's value 1 times level 1's headroom 2^h (0 = no shift);
+    // rows 1..L: zero, for the atomic max of each level
+    const int32_t h1 = g.L >= 2 ? headroom(g, p, 1) : 0;
     if (maxbits)
-        err = launch_fill_u32(maxbits, 0u, static_cast<int64_t>(g.L + 1) * w.S_pad, st);
+        err = launch_fill_u32(maxbits, h1 ? static_cast<uint32_t>(127 + h1) << 23 : 0u, w.S_pad, st);
+    if (maxbits && err == hipSuccess)
+        err = launch_fill_u32(maxbits + w.S_pad, 0u, static_cast<int64_t>(g.L) * w.S_pad, st);
     const void *prev = nullptr;  // level 0: the root, value 1
     for (int l = 1; l <= g.L - 1 && err == hipSuccess; ++l) {
         void *cur = bufs[(l - 1) & 1];
-        const uint32_t *pm = (maxbits && l >= 2) ? maxbits + static_cast<int64_t>(l - 1) * w.S_pad : nullptr;
+        const uint32_t *pm = maxbits ? maxbits + static_cast<int64_t>(l - 1) * w.S_pad : nullptr;
         uint32_t *cm = (maxbits && l <= g.L - 2) ? maxbits + static_cast<int64_t>(l) * w.S_pad : nullptr;
-        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, st);
+        const int32_t h_next = l <= g.L - 2 ? headroom(g, p, l + 1) : 0;
+        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st);
         prev = cur;
     }
     if (err == hipSuccess)
@@ -106,6 +120,11 @@ extern "C" cos_status cos_evaluate(const cos_graph *h, const double *x_dev, int6
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != g.device)
         return fail(COS_EINVAL, "cos_evaluate: the current device is not the graph's device");
+    if (value_bytes(p) == 2 && g.path == COS_PATH_FUSED)
+        return fail(COS_EINVAL, "cos_evaluate: 16-bit level storage runs on the streamed plan only");
+    if (p == COS_FP16_RESCALED && g.h16.empty())
+        return fail(COS_EINVAL, "cos_evaluate: binary16 storage needs rational factors with level row sums of "
+                                "|a| below 2^110 (use COS_BF16_RESCALED or COS_FP32_RESCALED)");
     Workspace w = plan_workspace(g, S, p);
     if (w.fused && !fused_fits(g, p))
         return fail(COS_EINVAL, "cos_evaluate: the fused plan was requested but the graph does not fit in LDS");

@@ -49,7 +49,11 @@ inline FusedLayout fused_layout(const Graph &g, size_t elem, bool rescale, int K
 
 // Largest samples-per-lane K in {4, 2, 1} whose accumulators fit in registers
 // and whose layout fits in LDS (0: the graph does not fit the fused plan).
+// 16-bit storage is a streamed-plan format (it halves HBM bytes; the fused
+// plan keeps levels on chip), so it never takes the fused plan.
 inline int fused_k(const Graph &g, cos_precision p) {
+    if (p != COS_FP64 && p != COS_FP32_RESCALED && p != COS_FP32)
+        return 0;
     const int rmax = rows_variant((g.max_width + kFusedWaves - 1) / kFusedWaves);
     if (rmax == 0)
         return 0;

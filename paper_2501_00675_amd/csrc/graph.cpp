@@ -165,6 +165,39 @@ cos_status validate_shape(int32_t L, const int64_t *widths, const int64_t *epl, 
 namespace {
 
 // Edge parameters of one of the two factor kinds.
+// Headroom exponents of binary16 level storage.  Rational factors satisfy
+// |w_e| <= |a_e| (the denominator is at least 1), so a level-l value is at
+// most R_l = max_j sum_{e into j} |a_e| times the largest value of level l-1.
+// The sweep normalises level l-1 to [1, 2) and stores level l times 2^-h_l
+// with h_l = max(0, ceil(log2 R_l) - 14): every stored value stays below
+// 2^15 (binary16 holds up to 65504).  Empty when some h_l would exceed
+// kMaxHeadroom16 (binary16 storage is then refused).
+std::vector<int32_t> headroom16(const Graph &G, const std::vector<int32_t> &row_ptr) {
+    std::vector<int32_t> h(static_cast<size_t>(G.L), 0);
+    for (int32_t l = 1; l <= G.L - 1; ++l) {
+        const LevelDesc &d = G.levels[l - 1];
+        const int32_t *r = row_ptr.data() + d.rp_begin;
+        double R = 0.0;
+        for (int64_t j = 0; j < d.w_dst; ++j) {
+            double sum = 0.0;
+            for (int64_t q = r[j]; q < r[j + 1]; ++q)
+                sum += std::fabs(G.h_a[q]);
+            R = std::max(R, sum);
+        }
+        if (!std::isfinite(R))
+            return {};
+        if (R > 0.0) {
+            int e = 0;
+            const double f = std::frexp(R, &e);  // R = f 2^e, f in [0.5, 1)
+            const int c = f == 0.5 ? e - 1 : e;  // ceil(log2 R)
+            h[l] = std::max(0, c - 14);
+            if (h[l] > kMaxHeadroom16)
+                return {};
+        }
+    }
+    return h;
+}
+
 struct EdgeParams {
     int32_t kind = FK_RATIONAL;
     const double *a = nullptr, *b = nullptr, *k = nullptr;  // rational
@@ -361,6 +394,8 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
         ldev[l - 1] = LevelDev{static_cast<int32_t>(d.w_dst), static_cast<int32_t>(d.rp_begin),
                                static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges)};
     }
+    if (!lookup)
+        G.h16 = headroom16(G, row_ptr);
 
     // one device allocation: row_ptr | edge record arrays | level table
     const size_t off_rp = 0;

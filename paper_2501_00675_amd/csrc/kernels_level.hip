@@ -62,15 +62,16 @@ __device__ __forceinline__ bool block_tile(int n_rg, int n_tiles, int xcd_group,
 // destination rows of the group's row range, for one tile of 64*K samples
 // (lane i handles samples tile*64K + i + 64m, m < K: every load and store
 // covers 64 consecutive values of one row); see level_wave_rows.
-// RESCALE: the rows are scaled by 2^-e_{l-1}[s], e_{l-1}[s] = ilogb of the
-// largest |value| of level l-1 for sample s (read from prev_max), and the
-// largest |value| of this level is folded into cur_max[s].
-template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE, int KIND>
+// RESCALE: the rows are scaled by 2^-e_{l-1}[s], e_{l-1}[s] = ilogb of
+// prev_max[s] (the largest |value| of level l-1 for sample s, times the
+// headroom of level l), and the largest |value| of this level, times 2^h_next,
+// is folded into cur_max[s].  V: storage type of the level values.
+template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE, int KIND, typename V>
 __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     const int32_t *__restrict__ row_ptr, const typename SweepPath<T, KIND>::Rec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
-    int32_t n_tiles, int32_t xcd_group, int32_t reverse_tiles, const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
+    int32_t n_tiles, int32_t xcd_group, int32_t reverse_tiles, const V *__restrict__ prev, V *__restrict__ cur, int64_t ld,
     const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
-    uint32_t *__restrict__ cur_max) {
+    uint32_t *__restrict__ cur_max, int32_t h_next) {
     int tile, rg;
     if (!block_tile(n_rg, n_tiles, xcd_group, reverse_tiles, tile, rg))
         return;
@@ -88,10 +89,14 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     }
     const int jbeg = min(rg * (4 * ROWS) + wave * ROWS, w_dst);
     const int jend = min(jbeg + ROWS, w_dst);
-    level_wave_rows<T, K, FROM_ROOT, RESCALE, KIND>(row_ptr, edges, jbeg, jend, prev, cur, ld, tbase, lane, smp,
-                                                    esh, lmax);
+    level_wave_rows<T, K, FROM_ROOT, RESCALE, KIND, V>(row_ptr, edges, jbeg, jend, prev, cur, ld, tbase, lane, smp,
+                                                       esh, lmax);
     if constexpr (RESCALE) {
         if (cur_max) {
+            if (h_next)  // exact: |value| <= 2^15 and h_next <= 96
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    lmax[m] = abs_bits(ldexpf(__uint_as_float(lmax[m]), h_next));
             __shared__ uint32_t red[4 * kWave * K];
             fold_max<K, 4>(red, lmax, wave, lane, cur_max + tbase);
         }
@@ -148,12 +153,12 @@ constexpr bool kAlternateTiles = true;  // tile-major launches alternate their t
 // Samples per lane of an interior level (tile = 64 K samples).  When the
 // tile's slice of the previous level fits in one XCD's L2, tiles are grouped
 // by XCD and the gathers hit L2: binary64 then takes K = 2 (half the registers
-// of K = 4, twice the waves per SIMD), binary32 the largest K in {4, 2} whose
-// slice fits.  Otherwise (wide levels) K = 4 amortises each record over the
-// most samples.  Measured on the mid and precision workloads.
-template <typename T>
+// of K = 4, twice the waves per SIMD), 32- and 16-bit storage the largest K in
+// {4, 2} whose slice fits.  Otherwise (wide levels) K = 4 amortises each
+// record over the most samples.  Measured on the mid and precision workloads.
+template <typename T, typename V>
 int level_k(int64_t w_src) {
-    const auto fits = [&](int K) { return w_src * kWave * K * static_cast<int64_t>(sizeof(T)) <= kL2Slice; };
+    const auto fits = [&](int K) { return w_src * kWave * K * static_cast<int64_t>(sizeof(V)) <= kL2Slice; };
     if (sizeof(T) == sizeof(double))
         return fits(2) ? 2 : 4;
     if (fits(4))
@@ -161,14 +166,15 @@ int level_k(int64_t w_src) {
     return fits(2) ? 2 : 4;
 }
 
-template <typename T, int K, bool RESCALE, int KIND>
+template <typename T, int K, bool RESCALE, int KIND, typename V>
 hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
-                          int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
+                          int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next,
+                          hipStream_t s) {
     const LevelDesc &d = g.levels[l - 1];
     const int32_t rows_per_group = 4 * kRows;
     const int64_t n_rg = (d.w_dst + rows_per_group - 1) / rows_per_group;
     const int64_t n_tiles = ld / (kWave * K);
-    const int32_t xcd_group = d.w_src * kWave * K * static_cast<int64_t>(sizeof(T)) <= kL2Slice ? 1 : 0;
+    const int32_t xcd_group = d.w_src * kWave * K * static_cast<int64_t>(sizeof(V)) <= kL2Slice ? 1 : 0;
     const int32_t reverse_tiles = kAlternateTiles && (l & 1) == 0 ? 1 : 0;
     const int64_t grid = (xcd_group ? round_up(n_tiles, kXcds) : n_tiles) * n_rg;
     if (grid <= 0)
@@ -185,27 +191,38 @@ hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, in
         recs = g.d_edges32;
     TimedLaunch tl(KK_LEVEL, s);
     if (prev == nullptr)
-        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, true, RESCALE, KIND>), dim3(grid), dim3(kBlock), 0, s, rp,
-                           recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
-                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, nullptr, static_cast<T *>(cur), ld,
-                           x, S, xs, prev_max, cur_max);
+        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, true, RESCALE, KIND, V>), dim3(grid), dim3(kBlock), 0, s,
+                           rp, recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
+                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, nullptr, static_cast<V *>(cur), ld,
+                           x, S, xs, prev_max, cur_max, h_next);
     else
-        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, false, RESCALE, KIND>), dim3(grid), dim3(kBlock), 0, s, rp,
-                           recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
-                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, static_cast<const T *>(prev),
-                           static_cast<T *>(cur), ld, x, S, xs, prev_max, cur_max);
+        hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, false, RESCALE, KIND, V>), dim3(grid), dim3(kBlock), 0, s,
+                           rp, recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
+                           static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, static_cast<const V *>(prev),
+                           static_cast<V *>(cur), ld, x, S, xs, prev_max, cur_max, h_next);
     return hipGetLastError();
 }
 
-template <typename T, bool RESCALE>
+// LOOKUP_OK: whether the storage type takes lookup factors (binary16 does not:
+// its headroom needs a bound on the factors).
+template <typename T, bool RESCALE, typename V = T, bool LOOKUP_OK = true>
 hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
-                          int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, hipStream_t s) {
-    const bool k2 = level_k<T>(g.levels[l - 1].w_src) == 2;
-    if (g.kind == FK_LOOKUP)
-        return k2 ? launch_level_k<T, 2, RESCALE, FK_LOOKUP>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s)
-                  : launch_level_k<T, 4, RESCALE, FK_LOOKUP>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
-    return k2 ? launch_level_k<T, 2, RESCALE, FK_RATIONAL>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s)
-              : launch_level_k<T, 4, RESCALE, FK_RATIONAL>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
+                          int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next,
+                          hipStream_t s) {
+    const bool k2 = level_k<T, V>(g.levels[l - 1].w_src) == 2;
+    if (g.kind == FK_LOOKUP) {
+        if constexpr (LOOKUP_OK)
+            return k2 ? launch_level_k<T, 2, RESCALE, FK_LOOKUP, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
+                                                                    h_next, s)
+                      : launch_level_k<T, 4, RESCALE, FK_LOOKUP, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
+                                                                    h_next, s);
+        else
+            return hipErrorInvalidValue;
+    }
+    return k2 ? launch_level_k<T, 2, RESCALE, FK_RATIONAL, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
+                                                              h_next, s)
+              : launch_level_k<T, 4, RESCALE, FK_RATIONAL, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
+                                                              h_next, s);
 }
 
 }  // namespace
@@ -216,14 +233,19 @@ int32_t final_chunk_count(int64_t final_in_degree) {
 
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
                         const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
-                        hipStream_t s) {
+                        int32_t h_next, hipStream_t s) {
     switch (p) {
     case COS_FP64:
-        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, s);
+        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s);
     case COS_FP32_RESCALED:
-        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, s);
+        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s);
     case COS_FP32:
-        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, s);
+        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s);
+    case COS_FP16_RESCALED:
+        return launch_level_t<float, true, _Float16, false>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, h_next,
+                                                            s);
+    case COS_BF16_RESCALED:
+        return launch_level_t<float, true, __bf16>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s);
     }
     return hipErrorInvalidValue;
 }
@@ -249,6 +271,15 @@ hipError_t launch_final_partial(const Graph &g, cos_precision p, const void *pre
     else if (p == COS_FP64)
         hipLaunchKernelGGL((final_partial_kernel<double, kKFinal, false, KIND>), grid, dim3(kBlock), 0, s, edges, ne,
                            chunks, static_cast<const double *>(prev), ld, x, S, xs, partial);
+    else if (p == COS_BF16_RESCALED)
+        hipLaunchKernelGGL((final_partial_kernel<__bf16, kKFinal, false, KIND>), grid, dim3(kBlock), 0, s, edges, ne,
+                           chunks, static_cast<const __bf16 *>(prev), ld, x, S, xs, partial);
+    else if (p == COS_FP16_RESCALED && KIND == FK_RATIONAL)
+        hipLaunchKernelGGL((final_partial_kernel<_Float16, kKFinal, false, FK_RATIONAL>), grid, dim3(kBlock), 0, s,
+                           g.d_edges + d.e_begin, ne, chunks, static_cast<const _Float16 *>(prev), ld, x, S, xs,
+                           partial);
+    else if (p == COS_FP16_RESCALED)
+        return hipErrorInvalidValue;
     else
         hipLaunchKernelGGL((final_partial_kernel<float, kKFinal, false, KIND>), grid, dim3(kBlock), 0, s, edges, ne,
                            chunks, static_cast<const float *>(prev), ld, x, S, xs, partial);
@@ -268,7 +299,7 @@ hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64
     TimedLaunch tl(KK_FINAL_COMBINE, s);
     const dim3 grid(static_cast<unsigned>((S + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(final_combine_kernel, grid, dim3(kBlock), 0, s, partial, chunks, ld, S,
-                       p == COS_FP32_RESCALED ? maxbits : nullptr, g.L, out, out_exp);
+                       is_rescaled(p) ? maxbits : nullptr, g.L, out, out_exp);
     return hipGetLastError();
 }
 

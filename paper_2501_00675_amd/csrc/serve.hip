@@ -107,10 +107,10 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     const int jend = min(jbeg + kServeLevelRows, lv.w_dst);
     const int32_t *rp = r.row_ptr + lv.rp_begin;
     if (l == 1)
-        level_wave_rows<T, K, true, RESCALE, FK_RATIONAL>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
+        level_wave_rows<T, K, true, RESCALE, FK_RATIONAL, T>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
                                              lmax);
     else
-        level_wave_rows<T, K, false, RESCALE, FK_RATIONAL>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
+        level_wave_rows<T, K, false, RESCALE, FK_RATIONAL, T>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
                                               lmax);
     if constexpr (RESCALE) {
         if (l <= r.L - 2)

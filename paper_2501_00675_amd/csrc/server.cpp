@@ -439,6 +439,8 @@ extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double
                                         double *out_dev, int32_t *out_exp_dev, uint64_t *ticket) {
     if (!h || !x_dev || !out_dev || !ticket)
         return fail(COS_EINVAL, "cos_server_submit: NULL argument");
+    if (p == COS_FP16_RESCALED || p == COS_BF16_RESCALED)
+        return fail(COS_EINVAL, "cos_server_submit: 16-bit level storage is not served (cos_evaluate only)");
     if (p != COS_FP64 && p != COS_FP32_RESCALED && p != COS_FP32)
         return fail(COS_EINVAL, "cos_server_submit: unknown precision");
     if (S < 1 || S > INT32_MAX)

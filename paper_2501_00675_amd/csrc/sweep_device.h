@@ -190,21 +190,24 @@ using FinalPath = SweepPath<double, KIND>;
 // FROM_ROOT: level 1, whose only source is the root (value 1).
 // RESCALE:   binary32 with per-(level, sample) power-of-two scaling: each
 //            stored value is its sum times 2^-esh[m] (exact), and lmax[m]
-//            collects the largest |stored value| bit pattern of the lane.
+//            collects the largest |stored value| bit pattern of the lane
+//            (taken before the rounding to V).
+// V:         storage type of the level values (T, or a 16-bit format under
+//            RESCALE): loads widen V to T exactly, stores round T to V.
 // Source rows are reached by 32-bit byte offsets (level buffers < 2 GiB).
-template <typename T, int K, bool FROM_ROOT, bool RESCALE, int KIND>
+template <typename T, int K, bool FROM_ROOT, bool RESCALE, int KIND, typename V = T>
 __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_ptr,
                                                 const typename SweepPath<T, KIND>::Rec *edges, int jbeg, int jend,
-                                                const T *__restrict__ prev, T *__restrict__ cur, int64_t ld,
+                                                const V *__restrict__ prev, V *__restrict__ cur, int64_t ld,
                                                 int64_t tbase, int lane,
                                                 const typename SweepPath<T, KIND>::template Samples<K> &xs,
                                                 const int (&esh)[K], uint32_t (&lmax)[K]) {
     using Rec = typename SweepPath<T, KIND>::Rec;
     if (jbeg >= jend)
         return;
-    T *const out_base = cur + tbase + lane;
+    V *const out_base = cur + tbase + lane;
     auto store_row = [&](int j, const T *acc) {
-        T *crow = out_base + static_cast<int64_t>(j) * ld;
+        V *crow = out_base + static_cast<int64_t>(j) * ld;
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             T z = acc[m];
@@ -212,7 +215,7 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
                 z = scale_pow2(z, esh[m]);
                 lmax[m] = max(lmax[m], abs_bits(z));
             }
-            crow[kWave * m] = z;
+            crow[kWave * m] = static_cast<V>(z);
         }
     };
     const ConstPtr<int32_t> rp = as_const(row_ptr);
@@ -230,8 +233,8 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
     }
     const Rec *rec = edges + e;
     const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
-    const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(T));
-    const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(T));
+    const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(V));
+    const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(V));
     constexpr int C = kStreamChunk<Rec>;
     // one chunk of the stream: records, source values and factors, then the
     // accumulation edge by edge (every edge of a full chunk, the first n of the
@@ -248,7 +251,7 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
             const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
 #pragma unroll
             for (int m = 0; m < K; ++m)
-                v[u][m] = FROM_ROOT ? T(1) : *reinterpret_cast<const T *>(row + m * kWave * sizeof(T));
+                v[u][m] = FROM_ROOT ? T(1) : static_cast<T>(*reinterpret_cast<const V *>(row + m * kWave * sizeof(V)));
         }
         T w[C][K];
 #pragma unroll
@@ -363,8 +366,11 @@ __device__ __forceinline__ void final_quarter(const typename FinalPath<KIND>::Re
 }
 
 // Final node, second pass for sample s: the chunk partial sums added in
-// ascending chunk order, then the binary32 path's accumulated exponent
-// E[s] = sum_{l=1}^{L-2} e_l[s] applied (or returned separately).
+// ascending chunk order, then the rescaled paths' accumulated exponent
+// E[s] = sum_{l=0}^{L-2} ilogb(maxbits[l][s]) applied (or returned
+// separately).  Row l >= 1 holds the largest |value| of level l (times the
+// next level's headroom 2^h, if any); row 0 is 2^h of level 1, or 0 (no
+// shift).
 __device__ __forceinline__ void final_combine_one(const double *__restrict__ partial, int32_t n_chunks, int64_t S_pad,
                                                   int64_t s, const uint32_t *__restrict__ maxbits, int32_t L,
                                                   double *__restrict__ out, int32_t *__restrict__ out_exp) {
@@ -373,7 +379,7 @@ __device__ __forceinline__ void final_combine_one(const double *__restrict__ par
         v += partial[static_cast<int64_t>(c) * S_pad + s];
     int E = 0;
     if (maxbits)
-        for (int l = 1; l <= L - 2; ++l)
+        for (int l = 0; l <= L - 2; ++l)
             E += ilogb_bits(maxbits[static_cast<int64_t>(l) * S_pad + s]);
     if (out_exp) {
         out[s] = v;

@@ -133,3 +133,36 @@ def test_zero_in_degree_and_empty_level(oracle_lib):
     g2 = LeveledGraph(np.array([1, 2, 1]), np.array([2, 0]), np.array([0, 0], np.int32),
                       np.array([1, 2], np.int32), np.ones(2), np.zeros(2), np.zeros((2, 3)))
     assert oracle.sweep(g2, np.zeros((3, 3)), lib=oracle_lib).tolist() == [0.0] * 3
+
+
+@pytest.mark.parametrize("factor", ["rational", "lookup"])
+@pytest.mark.parametrize("name", ["tiny", "mid"])
+def test_node_values_level_identity(oracle_lib, name, factor):
+    # forward node values v_n (root -> n) and backward ones G_n (n -> final,
+    # the forward values of the transposed graph): every level l cuts each
+    # path exactly once, so sum_{n in l} v_n G_n = V for every l
+    from workloads import transpose
+    from workloads.graphs import level_offsets
+
+    g, x = make_config(name, S=16, factor=factor)
+    v = oracle.node_values(g, x)
+    t = oracle.node_values(transpose(g), x)
+    V = oracle.sweep(g, x)
+    assert np.array_equal(v[-1], V) and np.all(v[0] == 1.0)
+    off, off_t = level_offsets(g.widths), level_offsets(g.widths[::-1])
+    for l in range(g.L + 1):
+        fw = v[off[l]:off[l + 1]]
+        bw = t[off_t[g.L - l]:off_t[g.L - l + 1]]  # (level l, i) <-> transposed (level L-l, i)
+        s = np.sum(fw * bw, axis=0)
+        assert np.all(np.abs(s - V) <= 1e-12 * np.sum(np.abs(fw * bw), axis=0)), l
+
+
+def test_node_values_count_paths(oracle_lib):
+    g, x = make_config("mid", S=2)
+    g = g.with_params(a=1.0, b=0.0)
+    count = np.zeros(g.n_nodes)
+    count[0] = 1.0
+    for s, d in zip(g.src.tolist(), g.dst.tolist()):  # level-major order
+        count[d] += count[s]
+    v = oracle.node_values(g, x)
+    assert np.all(v == count[:, None])
