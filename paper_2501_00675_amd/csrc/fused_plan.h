@@ -47,10 +47,22 @@ inline FusedLayout fused_layout(const Graph &g, size_t elem, bool rescale, int K
     return f;
 }
 
+// Lookup factors read each sample's table (n_slots binary64 entries) for
+// every edge; the tables of the tiles resident on one XCD (one workgroup per
+// CU, 32 CUs) should stay within half of its 4 MiB L2, else the entries are
+// fetched again from the Infinity Cache on every edge.
+constexpr int64_t kLookupL2Budget = int64_t(2) << 20;
+inline bool lookup_tables_fit(const Graph &g, int K) {
+    return g.kind != FK_LOOKUP ||
+           static_cast<int64_t>(g.n_slots) * kWave * K * static_cast<int64_t>(sizeof(double)) * 32 <= kLookupL2Budget;
+}
+
 // Largest samples-per-lane K in {4, 2, 1} whose accumulators fit in registers
-// and whose layout fits in LDS (0: the graph does not fit the fused plan).
-// 16-bit storage is a streamed-plan format (it halves HBM bytes; the fused
-// plan keeps levels on chip), so it never takes the fused plan.
+// and whose layout fits in LDS (0: the graph does not fit the fused plan); for
+// lookup factors also the largest whose resident tables fit in L2 (K = 1 is
+// always allowed).  16-bit storage is a streamed-plan format (it halves HBM
+// bytes; the fused plan keeps levels on chip), so it never takes the fused
+// plan.
 inline int fused_k(const Graph &g, cos_precision p) {
     if (p != COS_FP64 && p != COS_FP32_RESCALED && p != COS_FP32)
         return 0;
@@ -59,7 +71,8 @@ inline int fused_k(const Graph &g, cos_precision p) {
         return 0;
     const size_t elem = p == COS_FP64 ? sizeof(double) : sizeof(float);
     for (int K : {4, 2, 1})
-        if (acc_fits(elem, K, rmax) && fused_layout(g, elem, p == COS_FP32_RESCALED, K).total <= kLdsBytes)
+        if (acc_fits(elem, K, rmax) && fused_layout(g, elem, p == COS_FP32_RESCALED, K).total <= kLdsBytes &&
+            (K == 1 || lookup_tables_fit(g, K)))
             return K;
     return 0;
 }

@@ -374,13 +374,36 @@ __device__ __forceinline__ void final_quarter(const typename FinalPath<KIND>::Re
 __device__ __forceinline__ void final_combine_one(const double *__restrict__ partial, int32_t n_chunks, int64_t S_pad,
                                                   int64_t s, const uint32_t *__restrict__ maxbits, int32_t L,
                                                   double *__restrict__ out, int32_t *__restrict__ out_exp) {
+    // the loads of a group are issued together (they are independent); the
+    // additions stay in ascending chunk order
     double v = 0.0;
-    for (int c = 0; c < n_chunks; ++c)
+    int c = 0;
+    for (; c + 16 <= n_chunks; c += 16) {
+        double p[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            p[i] = partial[static_cast<int64_t>(c + i) * S_pad + s];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            v += p[i];
+    }
+    for (; c < n_chunks; ++c)
         v += partial[static_cast<int64_t>(c) * S_pad + s];
     int E = 0;
-    if (maxbits)
-        for (int l = 0; l <= L - 2; ++l)
+    if (maxbits) {
+        int l = 0;
+        for (; l + 8 <= L - 1; l += 8) {
+            uint32_t m[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                m[i] = maxbits[static_cast<int64_t>(l + i) * S_pad + s];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                E += ilogb_bits(m[i]);
+        }
+        for (; l <= L - 2; ++l)
             E += ilogb_bits(maxbits[static_cast<int64_t>(l) * S_pad + s]);
+    }
     if (out_exp) {
         out[s] = v;
         out_exp[s] = E;
