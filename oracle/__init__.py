@@ -6,6 +6,8 @@ never calls it.
 
   level_sweep.c  plain FP64 level-by-level evaluator (C, OpenMP over samples)
   path_sum.py    the definition itself: exact rational sum over all paths
+  mc.py          the Metropolis chain over sample configurations, with its
+                 counter-based generator (Philox4x64-10), step by step
 
 Functions here only marshal numpy arrays into the C evaluator.
 """
