@@ -1,6 +1,6 @@
 """Benchmark: edge-sample updates/s of the leveled-DAG level sweep on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload mid] [--precision fp64] [--no-serving]
+    python bench.py [--steps K] [--warmup W] [--workload mid] [--precision fp64] [--no-serving] [--no-mc]
 
 One step = one full evaluation (every level, the final-node reduction, and for
 the rescaled FP32 path the exponent bookkeeping) of the workload's graph for
@@ -10,7 +10,9 @@ oracle on the host cores; its outputs are also the reference for the reported
 error of the GPU results (every oracle call of this script happens in that leg,
 on outputs the other legs sampled).  The lookup leg ("lookup") times the same
 workload with the paper's own edge factor, a per-sample table entry times a
-sign.  The serving leg ("serving" in the JSON) replays the
+sign.  The Monte Carlo leg ("mc") runs one Metropolis walker per sample on the
+workload's graph and reports its step rate beside a plain evaluation.  The
+serving leg ("serving" in the JSON) replays the
 serving request stream through the continuous-batching server and through
 one-at-a-time evaluation, and reports p50/p99 request latency beside
 throughput.
@@ -306,12 +308,69 @@ def lookup_leg(P, args):
     return res, [check]
 
 
+MC_TEXT = ("Metropolis walkers for |V| (one per sample of the workload), uniform box proposals of half-width "
+           "{sigma}, Philox4x64-10 on the device; a step = propose + level sweep + accept")
+
+
+def mc_leg(P, args, eval_ms):
+    """Monte Carlo walkers on the workload's graph: one walker per sample, steps/s and edge-sample updates/s
+    including proposal and acceptance, against a plain evaluation of the same samples (eval_ms).  The oracle
+    re-runs the first walkers' chains in the CPU-baseline leg."""
+    import torch
+
+    from workloads import make_config
+
+    g, x = make_config(args.workload)
+    C, sigma, seed = x.shape[1], 0.5, 1
+    G = P.Graph.from_leveled(g)
+    res = {"workload": WORKLOAD_TEXT[args.workload] + "; " + MC_TEXT.format(sigma=sigma), "walkers": C}
+    n_check = min(C, 64)
+    check_steps = 8
+    for p in ("fp64", "fp32r"):
+        print(f"# mc {p}", file=sys.stderr, flush=True)
+        W = P.Walkers(G, torch.from_numpy(x).to("cuda:0"), p, seed=seed, sigma=sigma)
+        W.run(check_steps)  # also the warm-up; its state is what the oracle re-runs
+        torch.cuda.synchronize()
+        state = [t.cpu().numpy() for t in (W.x, W.accepted)] if p == "fp64" else None
+        W.reset_sums()
+        st = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(st)
+        W.run(args.steps)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        e = W.estimates()
+        res[p] = {"ms_per_step": ms, "value": g.n_edges * C / (ms / 1000.0), "steps_per_s": 1000.0 / ms,
+                  "walker_steps_per_s": C * 1000.0 / ms, "acceptance": e["acceptance"], "sign": e["sign"],
+                  "sign_se": e["sign_se"]}
+        if p in eval_ms:
+            res[p]["overhead_vs_evaluate"] = ms / eval_ms[p] - 1.0
+        if state is not None:
+            res["check"] = {"walkers": n_check, "steps": check_steps, "x": state[0][:, :n_check],
+                            "accepted": state[1][:n_check]}
+    chk = {"graph": g, "mc": True, "x0": np.ascontiguousarray(x[:, :n_check]), "seed": seed, "sigma": sigma,
+           "into": res}
+    return res, [chk]
+
+
 def reference_checks(checks):
     """Part of the CPU-baseline leg: the oracle's values on the sampled outputs of the other legs, and
     the resulting error statistics (written into each check's result dict)."""
     import oracle
 
     for c in checks:
+        if c.get("mc"):  # the oracle's chain for the first walkers: same positions and acceptances
+            from oracle import mc
+
+            ref = c["into"].pop("check")
+            xo, _, no, _ = mc.run(c["graph"], c["x0"], oracle.sweep(c["graph"], c["x0"]), 0, ref["steps"],
+                                  c["seed"], c["sigma"])
+            c["into"]["oracle_chain"] = {"walkers": ref["walkers"], "steps": ref["steps"],
+                                         "positions_bit_identical": bool(np.array_equal(xo, ref["x"])),
+                                         "accepted_equal": bool(np.array_equal(no, ref["accepted"]))}
+            continue
         V = oracle.sweep(c["graph"], c["x"], "value")
         Q = oracle.sweep(c["graph"], c["x"], "square")
         for p, y in c["y"].items():
@@ -465,6 +524,7 @@ def main():
                     help="edge-factor kind of the timed workload")
     ap.add_argument("--no-lookup", action="store_true", help="skip the lookup-factor block of the default run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo walkers leg")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=float, default=24.0)
@@ -520,6 +580,10 @@ def main():
         variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "kernels": kv,
                         "roofline": roofline(g, S_pad, pv, kv, args.steps, args.workload), "_y": outv.cpu().numpy()}
     checks = []
+    if args.factor == "rational" and not args.no_mc:
+        eval_ms = {args.precision: ms, **{k: v["ms_per_step"] for k, v in variants.items()}}
+        result["mc"], c = mc_leg(P, args, eval_ms)
+        checks += c
     if args.factor == "rational" and not args.no_lookup:
         result["lookup"], c = lookup_leg(P, args)
         checks += c

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define COS_ABI_VERSION 2
+#define COS_ABI_VERSION 3
 
 typedef enum cos_status {
     COS_OK = 0,
@@ -236,6 +236,59 @@ cos_status cos_evaluate(const cos_graph *g, const double *x_dev, int64_t S, cos_
 /* Release a graph and its device memory.  Must not race with queued work that
    reads it.  NULL is a no-op.  Errors: COS_EDEVICE if hipFree fails. */
 cos_status cos_destroy_graph(cos_graph *g);
+
+/* ------------------------------------------------------------- Monte Carlo
+ *
+ * Markov-chain walkers over sample configurations: the integration over the
+ * vertex coordinates by Monte Carlo sampling (Sec. II.B), with the walkers'
+ * configurations evaluated together as the samples of one sweep (Sec. II.C,
+ * "Distributing the task on a grid of blocks") and proposal and acceptance
+ * done on the device (Sec. IV).  Walker c holds x_c (a column of x_dev) and
+ * v_c = V(x_c).  One step t of every walker:
+ *
+ *   r_0..r_3 = Philox4x64-10 (Salmon et al., SC'11), counter (c, t, 0, 0),
+ *              key (seed, 0);  u_i = (r_i >> 11) * 2^-53
+ *   x'_i     = x_i + sigma * (2 u_i - 1), i < 3 (product and sum each rounded)
+ *   v'       = V(x') at precision p (the level sweep of cos_evaluate)
+ *   accept iff u_3 * |v| < |v'|   (Metropolis for the density |V|)
+ *   then at the walker's state: acc[0][c] += sign(v), acc[1][c] += |x|^2
+ *   (x0 x0 + x1 x1 + x2 x2, left to right), accepted[c] += 1 if accepted.
+ *
+ * The average of acc[0] over walkers and steps estimates int V / int |V|.
+ * Random numbers depend on (seed, c, t) only: splitting a run into calls
+ * (step0 = steps already done) or running a subset of walkers gives the same
+ * bits.
+ */
+
+/* Device scratch bytes cos_mc_run needs for C walkers at precision p (the
+   proposals, their values and the sweep's workspace).  Errors: COS_EINVAL. */
+cos_status cos_mc_workspace_size(const cos_graph *g, int64_t C, cos_precision p, uint64_t *bytes);
+
+/*
+ * Run steps step0 .. step0 + n_steps - 1 of C walkers on a graph with
+ * rational factors.
+ *
+ *   x_dev         device float64[3][C], in/out: the walkers' coordinates.
+ *   v_dev         device float64[C], in/out: V(x) of each walker at precision
+ *                 p (the caller evaluates the starting points with
+ *                 cos_evaluate; the run keeps it current).
+ *   accepted_dev  device int64[C], in/out: accepted proposals (added to).
+ *   acc_dev       device float64[2][C], in/out: sums of sign(v) and |x|^2
+ *                 over the steps (added to).
+ *   seed, sigma   generator key; proposal half-width (finite, >= 0).
+ *   workspace_dev, workspace_bytes
+ *                 at least cos_mc_workspace_size bytes, 256-byte aligned; NULL:
+ *                 allocated and freed in stream order.
+ *
+ * Asynchronous on `stream`; one propose launch, one sweep and one accept
+ * launch per step.  Errors: COS_EINVAL (NULL pointers, C outside 1..2^31,
+ * negative step0 or n_steps, bad sigma, lookup factors, a precision or plan
+ * the graph refuses, small or misaligned workspace), COS_ENOMEM, COS_EDEVICE.
+ * On error the walkers' state is unspecified.
+ */
+cos_status cos_mc_run(const cos_graph *g, cos_precision p, int64_t C, double *x_dev, double *v_dev,
+                      int64_t step0, int64_t n_steps, uint64_t seed, double sigma, int64_t *accepted_dev,
+                      double *acc_dev, void *workspace_dev, uint64_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------ serving
  *

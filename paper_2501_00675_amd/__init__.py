@@ -12,6 +12,7 @@ built.
 
 from ._lib import LIB, PRECISIONS, CosError  # noqa: F401
 from .graph import Graph, timing_enable, timing_read  # noqa: F401
+from .mc import Walkers  # noqa: F401
 from .server import Server, Ticket  # noqa: F401
 
-__all__ = ["Graph", "Server", "Ticket", "CosError", "PRECISIONS", "timing_enable", "timing_read", "LIB"]
+__all__ = ["Graph", "Server", "Ticket", "Walkers", "CosError", "PRECISIONS", "timing_enable", "timing_read", "LIB"]

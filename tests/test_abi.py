@@ -38,7 +38,7 @@ def test_build_id_matches_sources_and_abi_version():
     from paper_2501_00675_amd import _build
 
     assert P.LIB.cos_build_id().decode() == _build.source_hash()
-    assert P.LIB.cos_abi_version() == 2
+    assert P.LIB.cos_abi_version() == 3
 
 
 def _create(g, **over):
@@ -140,6 +140,16 @@ def test_server_rejects_null_and_bad_args():
     assert L.LIB.cos_server_cancel(None, 1) == -1
     assert L.LIB.cos_server_get_stats(None, None) == -1
     assert L.LIB.cos_server_destroy(None) == 0
+
+
+def test_mc_rejects_null_and_bad_args():
+    # argument checks that come before any device call
+    import paper_2501_00675_amd._lib as L
+
+    v = ctypes.c_uint64()
+    assert L.LIB.cos_mc_workspace_size(None, 16, 0, ctypes.byref(v)) == -1
+    assert L.LIB.cos_mc_run(None, 0, 16, None, None, 0, 1, 0, 1.0, None, None, None, 0, None) == -1
+    assert "NULL" in L.LIB.cos_last_error().decode()
 
 
 def test_no_cpu_fallback_in_product_path():
