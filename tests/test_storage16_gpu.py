@@ -174,3 +174,33 @@ def test_server_refuses_16bit(P, precision):
             srv.submit(gid, to_dev(x), precision)
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("precision", P16)
+def test_short_graphs_and_empty_rows(P, precision):
+    from workloads import LeveledGraph, layered_graph
+
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, (3, 100))
+    # L = 1: root joined to the final node by three parallel edges (no stored level)
+    g1 = LeveledGraph(np.array([1, 1]), np.array([3]), np.zeros(3, np.int32), np.ones(3, np.int32),
+                      np.array([0.5, -0.25, 2.0]), np.array([0.0, 1.0, 0.5]), np.zeros((3, 3)))
+    check_bound(g1, x, gpu_eval(P.Graph.from_leveled(g1), x, precision), precision, "L=1")
+    # L = 2: one stored level
+    g2 = layered_graph([1, 7, 1], [1, 7], rng)
+    g2 = g2.with_params(a=rng.uniform(-1, 1, g2.n_edges), b=rng.uniform(0, 2, g2.n_edges),
+                        k=rng.uniform(-1, 1, (g2.n_edges, 3)))
+    check_bound(g2, x, gpu_eval(P.Graph.from_leveled(g2), x, precision), precision, "L=2")
+    # rows without in-edges and a level whose nodes all lose their in-edges
+    g = layered_graph([1, 5, 6, 4, 1], [1, 2, 2, 4], rng, cover=False)
+    g = g.with_params(a=rng.uniform(-1, 1, g.n_edges), b=rng.uniform(0, 2, g.n_edges),
+                      k=rng.uniform(-1, 1, (g.n_edges, 3)))
+    keep = np.ones(g.n_edges, bool)
+    sl = g.level_slices()[2]
+    keep[sl.start:sl.start + 3] = False
+    g3 = LeveledGraph(g.widths, np.array([int(keep[s].sum()) for s in g.level_slices()]), g.src[keep],
+                      g.dst[keep], g.a[keep], g.b[keep], g.k[keep])
+    check_bound(g3, x, gpu_eval(P.Graph.from_leveled(g3), x, precision), precision, "zero-in-degree")
+    g4 = LeveledGraph(np.array([1, 2, 1]), np.array([2, 0]), np.zeros(2, np.int32), np.array([1, 2], np.int32),
+                      np.ones(2), np.zeros(2), np.zeros((2, 3)))
+    assert np.all(gpu_eval(P.Graph.from_leveled(g4), x, precision) == 0.0)
