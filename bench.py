@@ -350,6 +350,24 @@ def mc_leg(P, args, eval_ms):
         if state is not None:
             res["check"] = {"walkers": n_check, "steps": check_steps, "x": state[0][:, :n_check],
                             "accepted": state[1][:n_check]}
+    # a small graph is where launches would dominate: one launch for the whole run (fused plan) against
+    # three per step (the same chain on the streamed plan)
+    gt, xt = make_config("tiny", S=C)
+    small = {}
+    for path in ("auto", "streamed"):
+        Gt = P.Graph.from_leveled(gt).set_path(path)
+        W = P.Walkers(Gt, torch.from_numpy(xt).to("cuda:0"), "fp64", seed=seed, sigma=1.0)
+        W.run(10)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        W.run(200)
+        b.record()
+        torch.cuda.synchronize()
+        small[path] = a.elapsed_time(b) / 200
+    res["tiny_graph"] = {"walkers": C, "steps": 200, "ms_per_step_one_launch": small["auto"],
+                         "ms_per_step_three_launches": small["streamed"],
+                         "walker_steps_per_s": C * 1000.0 / small["auto"]}
     chk = {"graph": g, "mc": True, "x0": np.ascontiguousarray(x[:, :n_check]), "seed": seed, "sigma": sigma,
            "into": res}
     return res, [chk]

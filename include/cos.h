@@ -280,8 +280,9 @@ cos_status cos_mc_workspace_size(const cos_graph *g, int64_t C, cos_precision p,
  *                 at least cos_mc_workspace_size bytes, 256-byte aligned; NULL:
  *                 allocated and freed in stream order.
  *
- * Asynchronous on `stream`; one propose launch, one sweep and one accept
- * launch per step.  Errors: COS_EINVAL (NULL pointers, C outside 1..2^31,
+ * Asynchronous on `stream`.  A graph on the fused plan (see cos_graph_set_path)
+ * runs the whole call in one launch; others take a propose launch, a sweep and
+ * an accept launch per step; both give the same bits.  Errors: COS_EINVAL (NULL pointers, C outside 1..2^31,
  * negative step0 or n_steps, bad sigma, lookup factors, a precision or plan
  * the graph refuses, small or misaligned workspace), COS_ENOMEM, COS_EDEVICE.
  * On error the walkers' state is unspecified.

@@ -185,10 +185,22 @@ hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64
                         int32_t chunks, double *out, int32_t *out_exp, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
-// LDS-resident whole-graph sweep (kernels_fused.hip).
+// A whole run of Monte Carlo walkers (cos_mc_run): state x [3][C], v [C],
+// proposals xp [3][C] and their values vp [C], per-walker sums.
+struct McArgs {
+    double *x, *v, *xp, *vp;
+    int64_t C, step0, n_steps;
+    uint64_t seed;
+    double sigma;
+    int64_t *accepted;
+    double *acc;
+};
+
+// LDS-resident whole-graph sweep (kernels_fused.hip).  With mc, one launch
+// runs every step of the walkers instead (rational factors).
 bool fused_fits(const Graph &g, cos_precision p);
 hipError_t launch_fused(const Graph &g, cos_precision p, const double *x, int64_t S, double *out,
-                        int32_t *out_exp, hipStream_t s);
+                        int32_t *out_exp, hipStream_t s, const McArgs *mc = nullptr);
 
 int32_t final_chunk_count(int64_t final_in_degree);
 

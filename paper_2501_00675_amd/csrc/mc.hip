@@ -8,97 +8,38 @@
 //   r0..r3 = Philox4x64-10(counter (c, t, 0, 0), key (seed, 0))
 //   u_i    = (r_i >> 11) 2^-53
 //   x'     = x + sigma (2 u_{0..2} - 1)          proposal (product, then sum)
-//   v'     = V(x')                              the level sweep (cos_evaluate)
+//   v'     = V(x')                              the level sweep
 //   accept iff u_3 |v| < |v'|                   Metropolis for the density |V|
 //   acc[0] += sign v, acc[1] += |x|^2, accepted += take   (at the new state)
 //
 // Every random number is a function of (seed, walker, step) only, so a run
 // split into several calls, or over a subset of walkers, is bit-identical to
-// one call.
+// one call.  Graphs that take the fused plan run the whole call in one
+// launch (mc_fused_kernel: the walkers of a tile stay with one workgroup for
+// every step); others take three launches per step (propose, cos_evaluate,
+// accept).  Both give the same bits.
 #include <cmath>
 
-#include "cos_internal.h"
+#include "mc_device.h"
 
 namespace cosdag {
 namespace {
 
-constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull, kPhiloxM1 = 0xCA5A826395121157ull;
-constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull, kPhiloxW1 = 0xBB67AE8584CAA73Bull;
-
-// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
-// 64x64->128 multiplies, the key bumped by the Weyl constants between rounds.
-__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += kPhiloxW0;
-            k1 += kPhiloxW1;
-        }
-        const uint64_t hi0 = __umul64hi(kPhiloxM0, c[0]), lo0 = kPhiloxM0 * c[0];
-        const uint64_t hi1 = __umul64hi(kPhiloxM1, c[2]), lo1 = kPhiloxM1 * c[2];
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ __forceinline__ double unit_uniform(uint64_t r) { return static_cast<double>(r >> 11) * 0x1.0p-53; }
-
-__device__ __forceinline__ void walker_uniforms(uint64_t seed, int64_t c, int64_t t, double (&u)[4]) {
-    uint64_t w[4] = {static_cast<uint64_t>(c), static_cast<uint64_t>(t), 0ull, 0ull};
-    philox4x64_10(w, seed, 0ull);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        u[i] = unit_uniform(w[i]);
-}
-
-// x' = x + sigma (2 u - 1): the product and the sum each rounded (no fusion).
 __global__ __launch_bounds__(kBlock) void mc_propose_kernel(const double *__restrict__ x, double *__restrict__ xp,
                                                             int64_t C, int64_t t, uint64_t seed, double sigma) {
-#pragma clang fp contract(off)
     const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (c >= C)
-        return;
-    double u[4];
-    walker_uniforms(seed, c, t, u);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double step = sigma * (2.0 * u[i] - 1.0);
-        xp[i * C + c] = x[i * C + c] + step;
-    }
+    if (c < C)
+        mc_propose(x, xp, C, c, t, seed, sigma);
 }
 
-// Metropolis decision for |V| and the per-walker sums at the resulting state.
 __global__ __launch_bounds__(kBlock) void mc_accept_kernel(double *__restrict__ x, double *__restrict__ v,
                                                            const double *__restrict__ xp,
                                                            const double *__restrict__ vp, int64_t C, int64_t t,
                                                            uint64_t seed, int64_t *__restrict__ accepted,
                                                            double *__restrict__ acc) {
-#pragma clang fp contract(off)
     const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (c >= C)
-        return;
-    double u[4];
-    walker_uniforms(seed, c, t, u);
-    double v0 = v[c];
-    const double v1 = vp[c];
-    double x0 = x[c], x1 = x[C + c], x2 = x[2 * C + c];
-    if (u[3] * fabs(v0) < fabs(v1)) {
-        x0 = xp[c];
-        x1 = xp[C + c];
-        x2 = xp[2 * C + c];
-        x[c] = x0;
-        x[C + c] = x1;
-        x[2 * C + c] = x2;
-        v[c] = v1;
-        v0 = v1;
-        accepted[c] += 1;
-    }
-    acc[c] += static_cast<double>((v0 > 0.0) - (v0 < 0.0));
-    const double r2 = x0 * x0 + x1 * x1 + x2 * x2;
-    acc[C + c] += r2;
+    if (c < C)
+        mc_accept(x, v, xp, vp, C, c, t, seed, accepted, acc);
 }
 
 struct McLayout {
@@ -187,7 +128,13 @@ extern "C" cos_status cos_mc_run(const cos_graph *h, cos_precision p, int64_t C,
     void *ew = base + m.off_eval;
     const dim3 grid(static_cast<unsigned>((C + kBlock - 1) / kBlock));
     hipError_t err = hipSuccess;
-    for (int64_t t = step0; t < step0 + n_steps && st == COS_OK && err == hipSuccess; ++t) {
+    // graphs on the fused plan: the whole run in one launch (persistent walkers)
+    const bool fused = g.path != COS_PATH_STREAMED && fused_fits(g, p);
+    if (fused) {
+        const McArgs a{x_dev, v_dev, xp, vp, C, step0, n_steps, seed, sigma, accepted_dev, acc_dev};
+        err = launch_fused(g, p, xp, C, vp, nullptr, s, &a);
+    }
+    for (int64_t t = step0; !fused && t < step0 + n_steps && st == COS_OK && err == hipSuccess; ++t) {
         hipLaunchKernelGGL(mc_propose_kernel, grid, dim3(kBlock), 0, s, x_dev, xp, C, t, seed, sigma);
         err = hipGetLastError();
         if (err != hipSuccess)

@@ -63,6 +63,18 @@ def test_split_runs_and_streamed_plan_are_bit_identical(P):
     assert np.array_equal(sub[0], a[0][:, :100]) and np.array_equal(sub[2], a[2][:100])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32r", "fp32"])
+def test_persistent_run_matches_step_by_step(P, precision):
+    # graphs on the fused plan run a whole call in one launch; the streamed
+    # plan takes three launches per step: the chains must be the same bits
+    g, x = make_config("tiny", S=1000)
+    a, _ = walk(P, g, x, 30, seed=2, sigma=0.9, precision=precision)
+    b, _ = walk(P, g, x, 30, seed=2, sigma=0.9, precision=precision, path="streamed")
+    c, _ = walk(P, g, x, 30, seed=2, sigma=0.9, precision=precision, split=[1, 13, 16])
+    for p, q, r in zip(a, b, c):
+        assert np.array_equal(p, q) and np.array_equal(p, r)
+
+
 def test_zero_step_accepts_every_proposal(P):
     g, x = make_config("tiny", S=200)
     (xg, vg, ng, ag), _ = walk(P, g, x, 6, seed=1, sigma=0.0)
