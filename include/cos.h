@@ -370,6 +370,17 @@ cos_status cos_server_cancel(cos_server *srv, uint64_t ticket);
 /* Counters of the server's lifetime.  Errors: COS_EINVAL on NULL. */
 cos_status cos_server_get_stats(cos_server *srv, cos_server_stats *stats);
 
+/*
+ * Failure handling.  When the device set-up of a newly admitted request fails
+ * (its slot entry upload or exponent-row clear), that request alone ends with
+ * COS_EDEVICE and its slot and workspace are returned; the others go on.  A
+ * failed step launch fails every active request of the server.  For tests of
+ * that path without a device fault: make the set-up of the admission with
+ * this index (0-based, in admission order; -1: none) fail as if the upload
+ * had.  Errors: COS_EINVAL (NULL server, index < -1).
+ */
+cos_status cos_server_fail_admission(cos_server *srv, int64_t admission_index);
+
 /* Cancel queued requests, wait for admitted ones, stop the scheduling thread
    and free the server's device memory.  NULL is a no-op. */
 cos_status cos_server_destroy(cos_server *srv);

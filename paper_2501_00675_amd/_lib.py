@@ -32,7 +32,7 @@ EXPORTS = [
     "cos_graph_export_lookup",
     "cos_server_create", "cos_server_add_graph", "cos_server_submit", "cos_server_poll", "cos_server_wait",
     "cos_server_cancel", "cos_server_get_stats", "cos_server_destroy",
-    "cos_mc_workspace_size", "cos_mc_run",
+    "cos_mc_workspace_size", "cos_mc_run", "cos_server_fail_admission",
 ]
 PATHS = {"auto": 0, "streamed": 1, "fused": 2}
 FACTOR_KINDS = {0: "rational", 1: "lookup"}
@@ -118,6 +118,8 @@ def _bind(lib):
     lib.cos_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
     lib.cos_server_destroy.restype = i32
     lib.cos_server_destroy.argtypes = [p]
+    lib.cos_server_fail_admission.restype = i32
+    lib.cos_server_fail_admission.argtypes = [p, i64]
     lib.cos_mc_workspace_size.restype = i32
     lib.cos_mc_workspace_size.argtypes = [p, i64, i32, ctypes.POINTER(u64)]
     lib.cos_mc_run.restype = i32

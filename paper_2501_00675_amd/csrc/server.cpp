@@ -144,8 +144,13 @@ struct Server : cos_server {
     StepBuf bufs[2];
     std::thread worker;
 
+    int64_t admissions = 0;         // requests admitted so far (their admission index)
+    int64_t fail_admission_at = -1;  // test hook: this admission's set-up is made to fail
+
     ~Server();
     void run();
+    hipError_t setup(Request *r);
+    void fail_request(Request *r);
 };
 
 void step_done(void *p) {
@@ -200,12 +205,56 @@ uint32_t stage_items(const Request &r, int stage, uint32_t *n_rg, uint32_t *kind
     return static_cast<uint32_t>((r.S + kServeCombineTile - 1) / kServeCombineTile);
 }
 
+// Upload a newly admitted request's slot entry and clear its exponent rows.
+hipError_t Server::setup(Request *r) {
+    const Graph &g = *r->g;
+    ServeReqDev &d = h_reqs[r->slot];
+    d = ServeReqDev{};
+    d.row_ptr = g.d_row_ptr;
+    d.edges = g.d_edges;
+    d.edges32 = g.d_edges32;
+    d.levels = g.d_levels;
+    d.x = r->x;
+    d.out = r->out;
+    d.out_exp = r->out_exp;
+    d.ws = r->footprint ? d_arena + r->arena_off : nullptr;
+    d.S = r->S;
+    d.S_pad = r->fused ? 0 : r->wlay.S_pad;
+    d.off_buf0 = r->wlay.off_buf0;
+    d.off_buf1 = r->wlay.off_buf1;
+    d.off_maxbits = r->wlay.off_maxbits;
+    d.off_partial = r->wlay.off_partial;
+    d.L = g.L;
+    d.precision = r->p;
+    d.rows_variant = rows_variant((g.max_width + kFusedWaves - 1) / kFusedWaves);
+    d.final_chunks = r->wlay.final_chunks;
+    d.off_red = static_cast<uint32_t>(r->flay.off_red);
+    d.off_part = static_cast<uint32_t>(r->flay.off_part);
+    hipError_t err = hipMemcpyAsync(d_reqs + r->slot, &d, sizeof(ServeReqDev), hipMemcpyHostToDevice, stream);
+    if (err == hipSuccess && !r->fused && r->p == COS_FP32_RESCALED)
+        err = launch_fill_u32(reinterpret_cast<uint32_t *>(d.ws + d.off_maxbits), 0u,
+                              static_cast<int64_t>(g.L + 1) * r->wlay.S_pad, stream);
+    return err;
+}
+
+// Mark an active request failed and give back its slot and workspace (under the lock).
+void Server::fail_request(Request *r) {
+    r->state = RS_FAILED;
+    r->status = COS_EDEVICE;
+    r->t_done = now_ns();
+    ++st.failed;
+    if (r->footprint)
+        arena.release(r->arena_off, r->footprint);
+    slots[r->slot] = nullptr;
+}
+
 void Server::run() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
-        // ---- admission (host bookkeeping under the lock; device actions afterwards)
+        // ---- admission (host bookkeeping under the lock)
         std::vector<Request *> admitted;
+        std::vector<int64_t> admission_index;
         int free_slots = 0;
         for (Request *r : slots)
             free_slots += r == nullptr;
@@ -223,7 +272,27 @@ void Server::run() {
             r->t_admit = now_ns();
             --free_slots;
             admitted.push_back(r);
+            admission_index.push_back(admissions++);
             it = queue.erase(it);
+        }
+
+        // ---- slot entries of the admitted requests (device actions without the lock; stream order puts
+        // them before the step that first reads them).  A request whose set-up fails fails alone.
+        if (!admitted.empty()) {
+            const int64_t inject = fail_admission_at;
+            lk.unlock();
+            std::vector<Request *> failed;
+            for (size_t i = 0; i < admitted.size(); ++i) {
+                Request *r = admitted[i];
+                const hipError_t err = admission_index[i] == inject ? hipErrorUnknown : setup(r);
+                if (err != hipSuccess)
+                    failed.push_back(r);
+            }
+            lk.lock();
+            for (Request *r : failed)
+                fail_request(r);
+            if (!failed.empty())
+                cv.notify_all();
         }
         int active = 0;
         for (Request *r : slots)
@@ -233,7 +302,6 @@ void Server::run() {
 
         // ---- next step, if a table is free and some request has a stage left
         StepBuf *b = nullptr;
-        int64_t step_index = -1;
         for (StepBuf &cand : bufs)
             if (!cand.busy) {
                 b = &cand;
@@ -269,83 +337,47 @@ void Server::run() {
             t.items_streamed = items[1];
             b->busy = true;
             ++inflight;
-            step_index = st.steps++;
+            ++st.steps;
             st.items += items[0] + items[1];
             st.max_step_requests = std::max<int64_t>(st.max_step_requests, n);
         } else {
             b = nullptr;
         }
 
-        if (admitted.empty() && !b) {
-            if (stop && queue.empty() && inflight == 0) {
-                bool idle = true;
-                for (Request *r : slots)
-                    idle &= r == nullptr;
-                if (idle)
-                    break;
+        if (!b) {
+            if (admitted.empty()) {
+                if (stop && queue.empty() && inflight == 0) {
+                    bool idle = true;
+                    for (Request *r : slots)
+                        idle &= r == nullptr;
+                    if (idle)
+                        break;
+                }
+                cv.wait(lk);
             }
-            cv.wait(lk);
             continue;
         }
 
-        // ---- device actions without the lock (the completion callback takes it)
+        // ---- the step: one replay of the step graph, then the completion callback
         lk.unlock();
         hipError_t err = hipSuccess;
-        for (Request *r : admitted) {
-            const Graph &g = *r->g;
-            ServeReqDev &d = h_reqs[r->slot];
-            d = ServeReqDev{};
-            d.row_ptr = g.d_row_ptr;
-            d.edges = g.d_edges;
-            d.edges32 = g.d_edges32;
-            d.levels = g.d_levels;
-            d.x = r->x;
-            d.out = r->out;
-            d.out_exp = r->out_exp;
-            d.ws = r->footprint ? d_arena + r->arena_off : nullptr;
-            d.S = r->S;
-            d.S_pad = r->fused ? 0 : r->wlay.S_pad;
-            d.off_buf0 = r->wlay.off_buf0;
-            d.off_buf1 = r->wlay.off_buf1;
-            d.off_maxbits = r->wlay.off_maxbits;
-            d.off_partial = r->wlay.off_partial;
-            d.L = g.L;
-            d.precision = r->p;
-            d.rows_variant = rows_variant((g.max_width + kFusedWaves - 1) / kFusedWaves);
-            d.final_chunks = r->wlay.final_chunks;
-            d.off_red = static_cast<uint32_t>(r->flay.off_red);
-            d.off_part = static_cast<uint32_t>(r->flay.off_part);
-            if (err == hipSuccess)
-                err = hipMemcpyAsync(d_reqs + r->slot, &d, sizeof(ServeReqDev), hipMemcpyHostToDevice, stream);
-            if (err == hipSuccess && !r->fused && r->p == COS_FP32_RESCALED)
-                err = launch_fill_u32(reinterpret_cast<uint32_t *>(d.ws + d.off_maxbits), 0u,
-                                      static_cast<int64_t>(g.L + 1) * r->wlay.S_pad, stream);
-        }
-        if (b && err == hipSuccess) {
+        {
             TimedLaunch tl(KK_SERVE, stream);
             err = hipGraphLaunch(b->exec, stream);
         }
-        if (b && err == hipSuccess)
+        if (err == hipSuccess)
             err = hipLaunchHostFunc(stream, step_done, b);
         lk.lock();
         if (err != hipSuccess) {
-            // the device is unusable for this server: fail everything admitted
-            for (Request *&r : slots) {
-                if (!r)
-                    continue;
-                r->state = RS_FAILED;
-                r->status = COS_EDEVICE;
-                r->t_done = now_ns();
-                ++st.failed;
-                r = nullptr;
-            }
-            if (b) {
-                b->finishing.clear();
-                b->busy = false;
-                --inflight;
-            }
+            // the device is unusable for this server: fail every active request
+            for (Request *r : slots)
+                if (r)
+                    fail_request(r);
+            b->finishing.clear();
+            b->busy = false;
+            --inflight;
+            cv.notify_all();
         }
-        (void)step_index;
     }
 }
 
@@ -559,6 +591,17 @@ extern "C" cos_status cos_server_cancel(cos_server *h, uint64_t ticket) {
         ++s->st.cancelled;
     }
     s->cv.notify_all();
+    return COS_OK;
+}
+
+extern "C" cos_status cos_server_fail_admission(cos_server *h, int64_t admission_index) {
+    if (!h)
+        return fail(COS_EINVAL, "cos_server_fail_admission: server is NULL");
+    if (admission_index < -1)
+        return fail(COS_EINVAL, "cos_server_fail_admission: index must be >= -1");
+    Server *s = server_of(h);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fail_admission_at = admission_index;
     return COS_OK;
 }
 

@@ -117,6 +117,11 @@ class Server:
         check(st, "cos_server_cancel")
         return True
 
+    def fail_admission(self, admission_index: int) -> "Server":
+        """Test hook (cos_server_fail_admission): the admission with this index fails its set-up."""
+        check(LIB.cos_server_fail_admission(self.handle, int(admission_index)), "cos_server_fail_admission")
+        return self
+
     def stats(self) -> dict:
         s = ServerStats()
         check(LIB.cos_server_get_stats(self.handle, ctypes.byref(s)), "cos_server_get_stats")

@@ -127,6 +127,39 @@ def test_admission_waits_for_budget(P, precision):
         assert b["t_admit_ns"] >= a["t_done_ns"], "a request was admitted before the budget was free"
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_failed_setup_fails_only_that_request_and_frees_its_slot(P, precision):
+    # the set-up of the third admission is made to fail from the host (no device fault);
+    # with a budget for two requests at a time, a failed request that kept its workspace
+    # or slot would stall everything submitted after it
+    g, x = make_config("mid", S=2000, width=700, L=5, degree=3)
+    G = P.Graph.from_leveled(g)
+    W = G.workspace_bytes(2000, precision)
+    xs = [to_dev(x * (1.0 + 0.01 * i)) for i in range(8)]
+    torch.cuda.synchronize()
+    say(f"serve injected failure {precision} W={W}")
+    with P.Server(2 * W + W // 2, 2) as srv:
+        srv.fail_admission(2)
+        gid = srv.add_graph(G)
+        tickets = [srv.submit(gid, xs[i], precision, sync_inputs=False) for i in range(6)]
+        for i, t in enumerate(tickets):
+            if i == 2:
+                with pytest.raises(P.CosError) as e:
+                    srv.wait(t)
+                assert e.value.status == -3  # COS_EDEVICE
+            else:
+                assert srv.wait(t)["status"] == 0
+        later = [srv.submit(gid, xs[6 + i], precision, sync_inputs=False) for i in range(2)]
+        for t in later:
+            assert srv.wait(t)["status"] == 0
+        s = srv.stats()
+    assert s["failed"] == 1 and s["completed"] == 7 and s["max_active"] <= 2
+    for i, t in enumerate(tickets + later):
+        if i != 2:
+            ref = gpu_eval(G, xs[i].cpu().numpy(), precision)
+            assert np.array_equal(bits(t.out.cpu().numpy()), bits(ref)), i
+
+
 def test_request_that_never_fits_is_rejected(P):
     g, x = make_config("mid", S=2000, width=700, L=5, degree=3)
     G = P.Graph.from_leveled(g)
