@@ -1,0 +1,127 @@
+// Host-side scheduling core of the serving runtime, free of device calls so
+// that it can be exercised on its own: the workspace arena, admission of
+// queued requests by slot and footprint, and the composition of a step from
+// the active requests' next stages.  The server (server.cpp) drives it under
+// its lock; a request type only needs the fields used here.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <deque>
+#include <list>
+#include <utility>
+#include <vector>
+
+namespace cosdag {
+
+// First-fit allocator over [0, size) with coalescing, 256-byte granules.
+class Arena {
+  public:
+    static constexpr uint64_t kGranule = 256;
+    explicit Arena(uint64_t size) : size_(size) {
+        if (size)
+            free_.push_back({0, size});
+    }
+    static uint64_t granules(uint64_t n) { return (std::max<uint64_t>(n, 1) + kGranule - 1) / kGranule * kGranule; }
+    bool alloc(uint64_t n, uint64_t *off) {
+        n = granules(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                it->first += n;
+                it->second -= n;
+                if (it->second == 0)
+                    free_.erase(it);
+                used_ += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n) {
+        n = granules(n);
+        used_ -= n;
+        auto it = free_.begin();
+        while (it != free_.end() && it->first < off)
+            ++it;
+        it = free_.insert(it, {off, n});
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+    uint64_t size() const { return size_; }
+    const std::list<std::pair<uint64_t, uint64_t>> &free_blocks() const { return free_; }
+
+  private:
+    uint64_t size_;
+    uint64_t used_ = 0;
+    std::list<std::pair<uint64_t, uint64_t>> free_;  // (offset, bytes), sorted by offset
+};
+
+// Admit queued requests in order while a slot is free: a request whose
+// workspace (footprint bytes, 0 for none) does not fit in the arena now stays
+// queued without blocking the ones behind it.  Admitted requests get a slot
+// (the lowest free) and arena_off; returns them in admission order.
+// Req needs: footprint, arena_off, slot.
+template <class Req>
+std::vector<Req *> admit(std::deque<Req *> &queue, std::vector<Req *> &slots, Arena &arena) {
+    std::vector<Req *> admitted;
+    int free_slots = 0;
+    for (Req *r : slots)
+        free_slots += r == nullptr;
+    for (auto it = queue.begin(); it != queue.end() && free_slots > 0;) {
+        Req *r = *it;
+        uint64_t off = 0;
+        if (r->footprint && !arena.alloc(r->footprint, &off)) {
+            ++it;
+            continue;
+        }
+        r->arena_off = off;
+        r->slot = static_cast<int>(std::find(slots.begin(), slots.end(), nullptr) - slots.begin());
+        slots[r->slot] = r;
+        --free_slots;
+        admitted.push_back(r);
+        it = queue.erase(it);
+    }
+    return admitted;
+}
+
+// Compose one step: every active request with a stage left contributes its
+// next stage, whole-graph (fused) requests first, then the streamed ones,
+// each section in slot order; emit(section, request) is called for each in
+// that order, and the request's next_stage advances.  Returns how many
+// requests the step holds.  Req needs: fused, next_stage, n_stages.
+template <class Req, class Emit>
+int compose_step(const std::vector<Req *> &slots, Emit emit) {
+    int n = 0;
+    for (int section = 0; section < 2; ++section)
+        for (Req *r : slots) {
+            if (!r || r->next_stage >= r->n_stages || r->fused != (section == 0))
+                continue;
+            emit(section, r);
+            ++r->next_stage;
+            ++n;
+        }
+    return n;
+}
+
+// Whether some active request still has a stage to run.
+template <class Req>
+bool any_stage_left(const std::vector<Req *> &slots) {
+    for (Req *r : slots)
+        if (r && r->next_stage < r->n_stages)
+            return true;
+    return false;
+}
+
+}  // namespace cosdag

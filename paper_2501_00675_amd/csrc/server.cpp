@@ -19,6 +19,7 @@
 #include <unordered_map>
 
 #include "fused_plan.h"
+#include "serve_sched.h"
 #include "serve_types.h"
 
 namespace cosdag {
@@ -28,56 +29,6 @@ int64_t now_ns() {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
-
-// First-fit allocator over [0, size) with coalescing, 256-byte granules.
-class Arena {
-  public:
-    explicit Arena(uint64_t size) : size_(size) {
-        if (size)
-            free_.push_back({0, size});
-    }
-    bool alloc(uint64_t n, uint64_t *off) {
-        n = static_cast<uint64_t>(round_up(static_cast<int64_t>(std::max<uint64_t>(n, 1)), 256));
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                *off = it->first;
-                it->first += n;
-                it->second -= n;
-                if (it->second == 0)
-                    free_.erase(it);
-                used_ += n;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(uint64_t off, uint64_t n) {
-        n = static_cast<uint64_t>(round_up(static_cast<int64_t>(std::max<uint64_t>(n, 1)), 256));
-        used_ -= n;
-        auto it = free_.begin();
-        while (it != free_.end() && it->first < off)
-            ++it;
-        it = free_.insert(it, {off, n});
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    uint64_t used() const { return used_; }
-
-  private:
-    uint64_t size_;
-    uint64_t used_ = 0;
-    std::list<std::pair<uint64_t, uint64_t>> free_;  // (offset, bytes), sorted by offset
-};
 
 enum ReqState { RS_QUEUED, RS_ACTIVE, RS_DONE, RS_CANCELED, RS_FAILED };
 
@@ -253,27 +204,12 @@ void Server::run() {
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
         // ---- admission (host bookkeeping under the lock)
-        std::vector<Request *> admitted;
+        const std::vector<Request *> admitted = admit(queue, slots, arena);
         std::vector<int64_t> admission_index;
-        int free_slots = 0;
-        for (Request *r : slots)
-            free_slots += r == nullptr;
-        for (auto it = queue.begin(); it != queue.end() && free_slots > 0;) {
-            Request *r = *it;
-            uint64_t off = 0;
-            if (r->footprint && !arena.alloc(r->footprint, &off)) {
-                ++it;  // does not fit now; later requests may
-                continue;
-            }
-            r->arena_off = off;
-            r->slot = static_cast<int>(std::find(slots.begin(), slots.end(), nullptr) - slots.begin());
-            slots[r->slot] = r;
+        for (Request *r : admitted) {
             r->state = RS_ACTIVE;
             r->t_admit = now_ns();
-            --free_slots;
-            admitted.push_back(r);
             admission_index.push_back(admissions++);
-            it = queue.erase(it);
         }
 
         // ---- slot entries of the admitted requests (device actions without the lock; stream order puts
@@ -307,30 +243,23 @@ void Server::run() {
                 b = &cand;
                 break;
             }
-        bool any_stage = false;
-        for (Request *r : slots)
-            any_stage |= r && r->next_stage < r->n_stages;
-        if (b && any_stage) {
+        if (b && any_stage_left(slots)) {
             // whole-graph (fused) entries first, then level / final / combine entries
             StepTable &t = *b->h_tab;
             uint32_t n = 0, items[2] = {0, 0}, count[2] = {0, 0};
-            for (int section = 0; section < 2; ++section) {
-                for (Request *r : slots) {
-                    if (!r || r->next_stage >= r->n_stages || r->fused != (section == 0))
-                        continue;
-                    StepEntry &e = t.e[n++];
-                    e.slot = static_cast<uint32_t>(r->slot);
-                    e.n_items = stage_items(*r, r->next_stage, &e.n_rg, &e.kind, &e.level);
-                    e.item_base = items[section];
-                    items[section] += e.n_items;
-                    ++count[section];
-                    if (r->first_step < 0)
-                        r->first_step = st.steps;
-                    ++r->steps;
-                    if (++r->next_stage == r->n_stages)
-                        b->finishing.push_back(r);
-                }
-            }
+            compose_step(slots, [&](int section, Request *r) {
+                StepEntry &e = t.e[n++];
+                e.slot = static_cast<uint32_t>(r->slot);
+                e.n_items = stage_items(*r, r->next_stage, &e.n_rg, &e.kind, &e.level);
+                e.item_base = items[section];
+                items[section] += e.n_items;
+                ++count[section];
+                if (r->first_step < 0)
+                    r->first_step = st.steps;
+                ++r->steps;
+                if (r->next_stage + 1 == r->n_stages)
+                    b->finishing.push_back(r);
+            });
             t.n_fused = count[0];
             t.items_fused = items[0];
             t.n_streamed = count[1];
