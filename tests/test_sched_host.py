@@ -11,14 +11,22 @@ layout and that each request ends after exactly its stage count.
 import os
 import subprocess
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
+# host-only build with the system compiler (no device code): plain, and with
+# AddressSanitizer + UndefinedBehaviorSanitizer
+BUILDS = {"plain": [], "sanitized": ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]}
 
-def test_scheduler_invariants_under_fake_executor(tmp_path):
+
+@pytest.mark.parametrize("build", sorted(BUILDS))
+def test_scheduler_invariants_under_fake_executor(tmp_path, build):
     exe = tmp_path / "sched_check"
     src = os.path.join(ROOT, "tests", "host", "sched_check.cpp")
     inc = os.path.join(ROOT, "paper_2501_00675_amd", "csrc")
-    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", f"-I{inc}", src, "-o", str(exe)], check=True)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", *BUILDS[build], f"-I{inc}", src, "-o", str(exe)],
+                   check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "scheduler checks passed" in r.stdout
