@@ -449,6 +449,7 @@ def serving_leg(P, args):
     def batched(precision, arrivals_ns, n=None):
         n = len(reqs) if n is None else n
         before = srv.stats()
+        srv.read_steps()  # drop the trace of earlier runs
         P.timing_read("serve")
         P.timing_read("fill")
         P.timing_enable(True)
@@ -464,6 +465,9 @@ def serving_leg(P, args):
         after = srv.stats()
         P.timing_enable(False)
         step_ms, n_steps = P.timing_read("serve")
+        trace = srv.read_steps()
+        period = np.diff([r["t_done_ns"] for r in trace]) / 1e3  # completion-to-completion, µs
+        per_step = [r["n_fused"] + r["n_streamed"] for r in trace]
         done = np.array([d["t_done_ns"] for d in st], np.float64)
         lat = (done - (t0 + np.asarray(arrivals_ns[:n], np.float64))) / 1e6
         span = (done.max() - t0) / 1e9
@@ -471,7 +475,11 @@ def serving_leg(P, args):
                 "p99_ms": _pct(lat, 99), "steps": after["steps"] - before["steps"],
                 "step_graph_ms": step_ms, "mean_step_us": 1000.0 * step_ms / max(n_steps, 1),
                 "max_step_requests": after["max_step_requests"], "max_active": after["max_active"],
-                "peak_workspace_bytes": after["peak_bytes"]}
+                "peak_workspace_bytes": after["peak_bytes"],
+                "step_trace": {"steps": len(trace),
+                               "period_us_p50": _pct(period, 50) if len(period) else None,
+                               "period_us_p99": _pct(period, 99) if len(period) else None,
+                               "requests_per_step_p50": _pct(per_step, 50) if per_step else None}}
 
     def single(arrivals_ns, n=None):
         n = len(reqs) if n is None else n

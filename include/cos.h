@@ -317,6 +317,18 @@ typedef struct cos_req_stats {
     int64_t footprint;    /* device workspace bytes it holds while admitted */
 } cos_req_stats;
 
+/* One step of a server (the step trace).  With the requests' first_step and
+   steps (one stage per step, in consecutive steps), it tells which stage of
+   which request ran in which launch. */
+typedef struct cos_step_record {
+    int64_t step;          /* step index */
+    int64_t t_launch_ns;   /* steady clock: the step graph was queued */
+    int64_t t_done_ns;     /* steady clock: its completion callback ran */
+    int32_t n_fused;       /* requests with whole-graph work in the step */
+    int32_t n_streamed;    /* requests with a level, final-node or combine stage */
+    int64_t items;         /* work items of the step */
+} cos_step_record;
+
 typedef struct cos_server_stats {
     int64_t submitted, completed, cancelled, failed;
     int64_t steps;              /* step launches */
@@ -369,6 +381,14 @@ cos_status cos_server_cancel(cos_server *srv, uint64_t ticket);
 
 /* Counters of the server's lifetime.  Errors: COS_EINVAL on NULL. */
 cos_status cos_server_get_stats(cos_server *srv, cos_server_stats *stats);
+
+/*
+ * Step trace: copy the records of completed steps not read before, oldest
+ * first, up to cap of them, into out (host array); *n receives the count.
+ * The server keeps the last 65536 unread records (older ones are dropped).
+ * Errors: COS_EINVAL (NULL server or n, cap < 0, out NULL with cap > 0).
+ */
+cos_status cos_server_read_steps(cos_server *srv, cos_step_record *out, int64_t cap, int64_t *n);
 
 /*
  * Failure handling.  When the device set-up of a newly admitted request fails

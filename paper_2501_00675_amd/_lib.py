@@ -32,7 +32,7 @@ EXPORTS = [
     "cos_graph_export_lookup",
     "cos_server_create", "cos_server_add_graph", "cos_server_submit", "cos_server_poll", "cos_server_wait",
     "cos_server_cancel", "cos_server_get_stats", "cos_server_destroy",
-    "cos_mc_workspace_size", "cos_mc_run", "cos_server_fail_admission",
+    "cos_mc_workspace_size", "cos_mc_run", "cos_server_fail_admission", "cos_server_read_steps",
 ]
 PATHS = {"auto": 0, "streamed": 1, "fused": 2}
 FACTOR_KINDS = {0: "rational", 1: "lookup"}
@@ -62,6 +62,11 @@ class ServerStats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("steps", ctypes.c_int64), ("items", ctypes.c_int64),
                 ("max_active", ctypes.c_int64), ("max_step_requests", ctypes.c_int64),
                 ("budget_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64)]
+
+
+class StepRecord(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("n_fused", ctypes.c_int32), ("n_streamed", ctypes.c_int32), ("items", ctypes.c_int64)]
 
 
 def _hip_runtimes_mapped() -> set:
@@ -118,6 +123,8 @@ def _bind(lib):
     lib.cos_server_get_stats.argtypes = [p, ctypes.POINTER(ServerStats)]
     lib.cos_server_destroy.restype = i32
     lib.cos_server_destroy.argtypes = [p]
+    lib.cos_server_read_steps.restype = i32
+    lib.cos_server_read_steps.argtypes = [p, ctypes.POINTER(StepRecord), i64, ctypes.POINTER(i64)]
     lib.cos_server_fail_admission.restype = i32
     lib.cos_server_fail_admission.argtypes = [p, i64]
     lib.cos_mc_workspace_size.restype = i32

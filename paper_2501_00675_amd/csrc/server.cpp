@@ -59,8 +59,11 @@ struct StepBuf {
     hipGraphExec_t exec = nullptr;
     bool busy = false;
     std::vector<Request *> finishing;  // requests whose last stage is in this step
+    cos_step_record rec{};             // the step's trace record (t_done_ns set on completion)
     struct Server *srv = nullptr;
 };
+
+constexpr size_t kTraceKeep = 65536;  // unread step records kept
 
 }  // namespace
 }  // namespace cosdag
@@ -95,6 +98,7 @@ struct Server : cos_server {
     StepBuf bufs[2];
     std::thread worker;
 
+    std::deque<cos_step_record> trace;  // completed steps not read yet
     int64_t admissions = 0;         // requests admitted so far (their admission index)
     int64_t fail_admission_at = -1;  // test hook: this admission's set-up is made to fail
 
@@ -122,6 +126,10 @@ void step_done(void *p) {
             ++s->st.completed;
         }
         b->finishing.clear();
+        b->rec.t_done_ns = t;
+        s->trace.push_back(b->rec);
+        if (s->trace.size() > kTraceKeep)
+            s->trace.pop_front();
         b->busy = false;
         --s->inflight;
     }
@@ -264,6 +272,8 @@ void Server::run() {
             t.items_fused = items[0];
             t.n_streamed = count[1];
             t.items_streamed = items[1];
+            b->rec = cos_step_record{st.steps, now_ns(), 0, static_cast<int32_t>(count[0]),
+                                     static_cast<int32_t>(count[1]), static_cast<int64_t>(items[0]) + items[1]};
             b->busy = true;
             ++inflight;
             ++st.steps;
@@ -520,6 +530,22 @@ extern "C" cos_status cos_server_cancel(cos_server *h, uint64_t ticket) {
         ++s->st.cancelled;
     }
     s->cv.notify_all();
+    return COS_OK;
+}
+
+extern "C" cos_status cos_server_read_steps(cos_server *h, cos_step_record *out, int64_t cap, int64_t *n) {
+    if (!h || !n)
+        return fail(COS_EINVAL, "cos_server_read_steps: NULL argument");
+    if (cap < 0 || (cap > 0 && !out))
+        return fail(COS_EINVAL, "cos_server_read_steps: bad cap or out");
+    Server *s = server_of(h);
+    std::lock_guard<std::mutex> lk(s->mu);
+    int64_t k = 0;
+    while (k < cap && !s->trace.empty()) {
+        out[k++] = s->trace.front();
+        s->trace.pop_front();
+    }
+    *n = k;
     return COS_OK;
 }
 

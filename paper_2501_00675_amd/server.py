@@ -11,7 +11,8 @@ import ctypes
 
 import torch
 
-from ._lib import COS_EAGAIN, COS_ECANCELED, COS_EINVAL, COS_OK, LIB, PRECISIONS, CosError, ReqStats, ServerStats, check
+from ._lib import (COS_EAGAIN, COS_ECANCELED, COS_EINVAL, COS_OK, LIB, PRECISIONS, CosError, ReqStats, ServerStats,
+                   StepRecord, check)
 from .graph import Graph
 
 
@@ -116,6 +117,13 @@ class Server:
             return False
         check(st, "cos_server_cancel")
         return True
+
+    def read_steps(self, cap: int = 65536) -> list:
+        """Trace records of the steps completed since the last read (cos_server_read_steps), oldest first."""
+        buf = (StepRecord * max(int(cap), 1))()
+        n = ctypes.c_int64()
+        check(LIB.cos_server_read_steps(self.handle, buf, int(cap), ctypes.byref(n)), "cos_server_read_steps")
+        return [{f: getattr(buf[i], f) for f, _ in StepRecord._fields_} for i in range(n.value)]
 
     def fail_admission(self, admission_index: int) -> "Server":
         """Test hook (cos_server_fail_admission): the admission with this index fails its set-up."""

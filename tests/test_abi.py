@@ -140,6 +140,7 @@ def test_server_rejects_null_and_bad_args():
     assert L.LIB.cos_server_cancel(None, 1) == -1
     assert L.LIB.cos_server_get_stats(None, None) == -1
     assert L.LIB.cos_server_fail_admission(None, 0) == -1
+    assert L.LIB.cos_server_read_steps(None, None, 0, None) == -1
     assert L.LIB.cos_server_destroy(None) == 0
 
 

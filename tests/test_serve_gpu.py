@@ -79,7 +79,15 @@ def test_mix_bit_identical_to_evaluate_and_alone(P):
         stats = [srv.wait(t) for t in tickets]
         outs = [t.out.cpu().numpy() for t in tickets]
         s = srv.stats()
+        trace = srv.read_steps()
     assert all(st["status"] == 0 for st in stats)
+    # the step trace accounts for every step, every request's stages and every item
+    assert [r["step"] for r in trace] == list(range(s["steps"]))
+    assert all(r["t_done_ns"] >= r["t_launch_ns"] > 0 for r in trace)
+    assert sum(r["n_fused"] + r["n_streamed"] for r in trace) == sum(st["steps"] for st in stats)
+    assert sum(r["items"] for r in trace) == s["items"]
+    assert max(r["n_fused"] + r["n_streamed"] for r in trace) == s["max_step_requests"]
+    assert all(0 <= st["first_step"] and st["first_step"] + st["steps"] <= len(trace) for st in stats)
     for i, (y, r) in enumerate(zip(outs, refs)):
         assert np.array_equal(bits(y), bits(r)), f"request {i} ({jobs[i]['precision']}) differs from cos_evaluate"
     assert s["completed"] == len(jobs) and s["failed"] == 0
