@@ -47,6 +47,10 @@ class Graph:
                                       ptr(b, np.float64), ptr(np.reshape(k, -1), np.float64), ctypes.byref(h))
             check(st, "cos_create_graph")
         self._h = h
+        # host copy of the level sizes (for save)
+        self._L = int(L)
+        self._widths = np.array(widths, dtype=np.int64)
+        self._epl = np.array(edges_per_level, dtype=np.int64)
 
     @classmethod
     def from_leveled(cls, g) -> "Graph":
@@ -96,6 +100,23 @@ class Graph:
         check(LIB.cos_graph_export(self.handle, *[out[n].ctypes.data_as(ctypes.c_void_p)
                                                   for n in ("src", "dst", "a", "b", "k")]), "cos_graph_export")
         return out
+
+    def save(self, path) -> None:
+        """Write the graph to a .npz file: level sizes and the canonical edge lists (export()).
+        Graph.load re-creates it; the canonical order makes the re-created graph, and every
+        result on it, bit-identical."""
+        info = self.info()
+        np.savez(path, L=np.int64(self._L), widths=self._widths, epl=self._epl, kind=np.str_(info["kind"]),
+                 n_slots=np.int64(info["n_inputs"]), **self.export())
+
+    @classmethod
+    def load(cls, path) -> "Graph":
+        """Re-create a graph written by save() (plain arrays only: nothing in the file is executed)."""
+        with np.load(path, allow_pickle=False) as z:
+            if str(z["kind"]) == "lookup":
+                return cls(int(z["L"]), z["widths"], z["epl"], z["src"], z["dst"], slot=z["slot"], coef=z["coef"],
+                           n_slots=int(z["n_slots"]))
+            return cls(int(z["L"]), z["widths"], z["epl"], z["src"], z["dst"], z["a"], z["b"], z["k"])
 
     def workspace_bytes(self, S: int, precision: str = "fp64") -> int:
         v = ctypes.c_uint64()

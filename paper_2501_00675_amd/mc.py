@@ -47,6 +47,37 @@ class Walkers:
         self.step = 0          # global step index of the next step
         self.steps_summed = 0  # steps in the current sums
 
+    def save(self, path) -> None:
+        """Checkpoint the walkers (positions, values, sums, step index, seed, sigma) to a .npz file.
+        Random numbers depend on (seed, walker, step) only, so Walkers.load(...).run(n) continues
+        with exactly the bits an uninterrupted run would produce."""
+        self.stream.synchronize()
+        np.savez(path, x=self.x.cpu().numpy(), v=self.v.cpu().numpy(), accepted=self.accepted.cpu().numpy(),
+                 acc=self.acc.cpu().numpy(), step=np.int64(self.step), steps_summed=np.int64(self.steps_summed),
+                 seed=np.uint64(self.seed), sigma=np.float64(self.sigma), precision=np.str_(self.precision))
+
+    @classmethod
+    def load(cls, graph: Graph, path, stream: torch.cuda.Stream | None = None) -> "Walkers":
+        """Walkers restored from save() on the same graph (plain arrays only: nothing in the file is executed)."""
+        with np.load(path, allow_pickle=False) as z:
+            st = {k: z[k] for k in z.files}
+        dev = torch.device("cuda", torch.cuda.current_device())
+        w = cls.__new__(cls)
+        w.graph, w.precision, w.seed, w.sigma = graph, str(st["precision"]), int(st["seed"]), float(st["sigma"])
+        w.x = torch.from_numpy(np.ascontiguousarray(st["x"])).to(dev)
+        w.C = int(w.x.shape[1])
+        w.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        w.v = torch.from_numpy(np.ascontiguousarray(st["v"])).to(dev)
+        w.accepted = torch.from_numpy(np.ascontiguousarray(st["accepted"])).to(dev)
+        w.acc = torch.from_numpy(np.ascontiguousarray(st["acc"])).to(dev)
+        nb = ctypes.c_uint64()
+        check(LIB.cos_mc_workspace_size(graph.handle, w.C, PRECISIONS[w.precision], ctypes.byref(nb)),
+              "cos_mc_workspace_size")
+        w.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+        w.step, w.steps_summed = int(st["step"]), int(st["steps_summed"])
+        torch.cuda.synchronize(dev)
+        return w
+
     def run(self, n_steps: int) -> "Walkers":
         check(LIB.cos_mc_run(self.graph.handle, PRECISIONS[self.precision], self.C, self.x.data_ptr(),
                              self.v.data_ptr(), self.step, int(n_steps), self.seed, self.sigma,

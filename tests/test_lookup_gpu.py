@@ -187,3 +187,13 @@ def test_wrong_input_rows_rejected_and_server_refuses(P):
     with P.Server(1 << 20, 2) as srv:
         with pytest.raises(P.CosError):
             srv.add_graph(G)
+
+
+def test_lookup_graph_file_round_trip_bit_identical(P, tmp_path):
+    g, T = make_config("mid", S=512, factor="lookup")
+    G = P.Graph.from_leveled(g)
+    G.save(tmp_path / "g.npz")
+    G2 = P.Graph.load(tmp_path / "g.npz")
+    assert G2.info()["kind"] == "lookup" and G2.n_inputs == g.n_slots
+    for precision in ("fp64", "fp32r"):
+        assert np.array_equal(gpu_eval(G, T, precision), gpu_eval(G2, T, precision))

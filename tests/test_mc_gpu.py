@@ -118,3 +118,23 @@ def test_mc_argument_errors(P):
     st = P.LIB.cos_mc_run(G.handle, 0, 0, xd.data_ptr(), v.data_ptr(), 0, 1, 0, 1.0, n.data_ptr(), acc.data_ptr(),
                           None, 0, None)
     assert st == -1 and "C must be" in P.LIB.cos_last_error().decode()
+
+
+def test_checkpoint_and_graph_file_resume_bit_identical(P, tmp_path):
+    # a run interrupted after 7 steps, with the graph and the walkers written to files and
+    # re-created, continues with the bits of the uninterrupted run
+    g, x = make_config("mid", S=700)
+    whole, _ = walk(P, g, x, 15, seed=4, sigma=0.6, split=[7, 8])
+    G = P.Graph.from_leveled(g)
+    W = P.Walkers(G, to_dev(x), "fp64", seed=4, sigma=0.6).run(7)
+    G.save(tmp_path / "graph.npz")
+    W.save(tmp_path / "walkers.npz")
+    G2 = P.Graph.load(tmp_path / "graph.npz")
+    for k, v in G.export().items():
+        assert np.array_equal(v, G2.export()[k])
+    W2 = P.Walkers.load(G2, tmp_path / "walkers.npz").run(8)
+    torch.cuda.synchronize()
+    got = (W2.x.cpu().numpy(), W2.v.cpu().numpy(), W2.accepted.cpu().numpy(), W2.acc.cpu().numpy())
+    for p, q in zip(whole, got):
+        assert np.array_equal(p, q)
+    assert W2.step == 15
