@@ -348,9 +348,10 @@ typedef struct cos_server_stats {
  */
 cos_status cos_server_create(uint64_t hbm_budget, int32_t max_slots, cos_server **out);
 
-/* Register a graph (it must outlive the server) and get its id.
-   Errors: COS_EINVAL (NULL, graph on another device, graph with lookup
-   factors: those are evaluated with cos_evaluate). */
+/* Register a graph (it must outlive the server) and get its id.  Either
+   factor kind: a request on a lookup graph passes its samples' tables as x
+   ([n_slots][S], as cos_evaluate).  Errors: COS_EINVAL (NULL, graph on
+   another device). */
 cos_status cos_server_add_graph(cos_server *srv, const cos_graph *g, int32_t *gid);
 
 /*

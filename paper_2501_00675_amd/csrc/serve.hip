@@ -3,11 +3,13 @@
 // request's levels in order while different requests share the launch, the
 // many configurations in flight of Sec. II.C and Sec. III).
 //
-// A step is a graph of three nodes: the upload of the step table, then two
-// independent kernels that read it.  serve_fused_kernel (16 waves, levels in
+// A step is a graph: the upload of the step table, then independent kernels
+// that read it, one per section.  serve_fused_kernel (16 waves, levels in
 // LDS) sweeps whole narrow graphs, 64 samples per item; serve_stream_kernel
 // (4 waves, the shape of the standalone streamed kernels) runs one interior
 // level, the final-node partial sums or the final combine of the wide graphs.
+// Each is instantiated per edge-factor kind (rational, lookup), so that the
+// rational kernels keep their own register budget.
 // Work items are numbered per section and taken grid-stride.  Every item runs
 // the same device routines as the standalone kernels, so a request's result is
 // bit-identical to cos_evaluate alone, whatever it shares a step with.
@@ -37,45 +39,45 @@ __device__ __forceinline__ uint32_t find_entry(const StepTable *__restrict__ t, 
     return lo;
 }
 
-template <typename T, int RMAX, bool RESCALE>
+template <typename T, int RMAX, bool RESCALE, int KIND>
 __device__ __forceinline__ void serve_fused(const ServeReqDev &r, uint32_t tile, unsigned char *lds, int wave,
                                             int lane) {
     if constexpr (acc_fits(sizeof(T), 1, RMAX)) {
-        const FusedGraph G{r.row_ptr, r.edges, r.edges32, nullptr, r.levels, r.L, r.x, r.S, r.out, r.out_exp};
-        fused_tile<T, 1, RMAX, RESCALE, FK_RATIONAL>(G, static_cast<int64_t>(tile) * kWave, reinterpret_cast<T *>(lds),
-                                        reinterpret_cast<uint32_t *>(lds + r.off_red),
-                                        reinterpret_cast<double *>(lds + r.off_part), wave, lane);
+        const FusedGraph G{r.row_ptr, r.edges, r.edges32, r.edgesL, r.levels, r.L, r.x, r.S, r.out, r.out_exp};
+        fused_tile<T, 1, RMAX, RESCALE, KIND>(G, static_cast<int64_t>(tile) * kWave, reinterpret_cast<T *>(lds),
+                                              reinterpret_cast<uint32_t *>(lds + r.off_red),
+                                              reinterpret_cast<double *>(lds + r.off_part), wave, lane);
     }
 }
 
-template <typename T, bool RESCALE>
+template <typename T, bool RESCALE, int KIND>
 __device__ __forceinline__ void serve_fused_rows(const ServeReqDev &r, uint32_t tile, unsigned char *lds, int wave,
                                                  int lane) {
     switch (r.rows_variant) {
     case 2:
-        serve_fused<T, 2, RESCALE>(r, tile, lds, wave, lane);
+        serve_fused<T, 2, RESCALE, KIND>(r, tile, lds, wave, lane);
         break;
     case 4:
-        serve_fused<T, 4, RESCALE>(r, tile, lds, wave, lane);
+        serve_fused<T, 4, RESCALE, KIND>(r, tile, lds, wave, lane);
         break;
     case 8:
-        serve_fused<T, 8, RESCALE>(r, tile, lds, wave, lane);
+        serve_fused<T, 8, RESCALE, KIND>(r, tile, lds, wave, lane);
         break;
     case 16:
-        serve_fused<T, 16, RESCALE>(r, tile, lds, wave, lane);
+        serve_fused<T, 16, RESCALE, KIND>(r, tile, lds, wave, lane);
         break;
     case 24:
-        serve_fused<T, 24, RESCALE>(r, tile, lds, wave, lane);
+        serve_fused<T, 24, RESCALE, KIND>(r, tile, lds, wave, lane);
         break;
     default:
-        serve_fused<T, kMaxRows, RESCALE>(r, tile, lds, wave, lane);
+        serve_fused<T, kMaxRows, RESCALE, KIND>(r, tile, lds, wave, lane);
         break;
     }
 }
 
 // Interior level l for a row group of 32 rows (8 per wave) and a tile of 256
 // samples; the level buffers alternate as in the standalone sweep.
-template <typename T, bool RESCALE>
+template <typename T, bool RESCALE, int KIND>
 __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_t local, uint32_t n_rg,
                                             uint32_t *red, int wave, int lane) {
     constexpr int K = kServeLevelK;
@@ -88,10 +90,12 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     T *cur = (l - 1) & 1 ? b1 : b0;
     const T *prev = (l - 2) & 1 ? b1 : b0;
     uint32_t *maxbits = reinterpret_cast<uint32_t *>(r.ws + r.off_maxbits);
-    typename SweepPath<T, FK_RATIONAL>::template Samples<K> smp;
+    typename SweepPath<T, KIND>::template Samples<K> smp;
     smp.load(r.x, r.S, r.S, tbase, lane);
-    const typename SweepPath<T, FK_RATIONAL>::Rec *recs;
-    if constexpr (sizeof(T) == sizeof(double))
+    const typename SweepPath<T, KIND>::Rec *recs;
+    if constexpr (KIND == FK_LOOKUP)
+        recs = r.edgesL;
+    else if constexpr (sizeof(T) == sizeof(double))
         recs = r.edges;
     else
         recs = r.edges32;
@@ -107,11 +111,11 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     const int jend = min(jbeg + kServeLevelRows, lv.w_dst);
     const int32_t *rp = r.row_ptr + lv.rp_begin;
     if (l == 1)
-        level_wave_rows<T, K, true, RESCALE, FK_RATIONAL, T>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp, esh,
-                                             lmax);
+        level_wave_rows<T, K, true, RESCALE, KIND, T>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp,
+                                                      esh, lmax);
     else
-        level_wave_rows<T, K, false, RESCALE, FK_RATIONAL, T>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp, esh,
-                                              lmax);
+        level_wave_rows<T, K, false, RESCALE, KIND, T>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp,
+                                                       esh, lmax);
     if constexpr (RESCALE) {
         if (l <= r.L - 2)
             fold_max<K, 4>(red, lmax, wave, lane, maxbits + static_cast<int64_t>(l) * r.S_pad + tbase);
@@ -121,25 +125,29 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
 // Final-node partial sums of one chunk of 256 edges (wave w: quarter w) for a
 // tile of 128 samples, combined as ((q0 + q1) + q2) + q3 exactly as
 // final_partial_kernel does.
-template <typename TV>
+template <typename TV, int KIND>
 __device__ __forceinline__ void serve_final(const ServeReqDev &r, uint32_t local, double *red, int wave, int lane) {
     constexpr int K = kServeFinalK;
     const uint32_t n_chunks = static_cast<uint32_t>(r.final_chunks);
     const int c = static_cast<int>(local % n_chunks);
     const int64_t tbase = static_cast<int64_t>(local / n_chunks) * (kWave * K);
     const LevelDev lf = load_level(r.levels, r.L - 1);
-    LaneSamples<K> smp;
+    typename FinalPath<KIND>::template Samples<K> smp;
     smp.load(r.x, r.S, r.S, tbase, lane);
     const int c_end = min((c + 1) * kFinalChunk, lf.n_edges);
     const int e_lo = min(c * kFinalChunk + wave * kQuarter, c_end);
     const int e_hi = min(e_lo + kQuarter, c_end);
     double acc[K];
-    const EdgeRec *edges = r.edges + lf.e_begin;
+    const typename FinalPath<KIND>::Rec *edges;
+    if constexpr (KIND == FK_LOOKUP)
+        edges = r.edgesL + lf.e_begin;
+    else
+        edges = r.edges + lf.e_begin;
     if (r.L == 1) {
-        final_quarter<double, K, true, FK_RATIONAL>(edges, e_lo, e_hi, nullptr, r.S_pad, tbase, lane, smp, acc);
+        final_quarter<double, K, true, KIND>(edges, e_lo, e_hi, nullptr, r.S_pad, tbase, lane, smp, acc);
     } else {
         const TV *prev = reinterpret_cast<const TV *>(r.ws + ((r.L - 2) & 1 ? r.off_buf1 : r.off_buf0));
-        final_quarter<TV, K, false, FK_RATIONAL>(edges, e_lo, e_hi, prev, r.S_pad, tbase, lane, smp, acc);
+        final_quarter<TV, K, false, KIND>(edges, e_lo, e_hi, prev, r.S_pad, tbase, lane, smp, acc);
     }
 #pragma unroll
     for (int m = 0; m < K; ++m)
@@ -151,36 +159,42 @@ __device__ __forceinline__ void serve_final(const ServeReqDev &r, uint32_t local
             ((red[i] + red[kWave * K + i]) + red[2 * kWave * K + i]) + red[3 * kWave * K + i];
 }
 
+// Whole-graph items of section SEC (SS_FUSED, or SS_FUSED_LOOKUP with KIND lookup).
+template <int KIND, uint32_t SEC>
 __global__ __launch_bounds__(kFusedThreads) void serve_fused_kernel(const StepTable *__restrict__ tab,
                                                                     const ServeReqDev *__restrict__ reqs) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t n = tab->n_fused;
-    const uint32_t total = tab->items_fused;
+    const uint32_t lo = section_begin(*tab, SEC);
+    const uint32_t n = tab->n[SEC];
+    const uint32_t total = tab->items[SEC];
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const StepEntry &en = tab->e[find_entry(tab, 0, n, item)];
+        const StepEntry &en = tab->e[find_entry(tab, lo, n, item)];
         const ServeReqDev &r = reqs[en.slot];
         const uint32_t tile = item - en.item_base;
         if (r.precision == COS_FP64)
-            serve_fused_rows<double, false>(r, tile, lds, wave, lane);
+            serve_fused_rows<double, false, KIND>(r, tile, lds, wave, lane);
         else if (r.precision == COS_FP32_RESCALED)
-            serve_fused_rows<float, true>(r, tile, lds, wave, lane);
+            serve_fused_rows<float, true, KIND>(r, tile, lds, wave, lane);
         else
-            serve_fused_rows<float, false>(r, tile, lds, wave, lane);
+            serve_fused_rows<float, false, KIND>(r, tile, lds, wave, lane);
         // fused_tile ends with a group barrier, so LDS is free for the next item
     }
 }
 
+// Level, final-node and combine items of section SEC (SS_STREAMED, or
+// SS_STREAMED_LOOKUP with KIND lookup).
+template <int KIND, uint32_t SEC>
 __global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *__restrict__ tab,
                                                               const ServeReqDev *__restrict__ reqs) {
     __shared__ __align__(16) unsigned char lds[4 * kWave * kServeLevelK * sizeof(uint32_t)];
     static_assert(sizeof(lds) >= 4 * kWave * kServeFinalK * sizeof(double), "final-node staging");
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t lo = tab->n_fused;
-    const uint32_t n = tab->n_streamed;
-    const uint32_t total = tab->items_streamed;
+    const uint32_t lo = section_begin(*tab, SEC);
+    const uint32_t n = tab->n[SEC];
+    const uint32_t total = tab->items[SEC];
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
         const StepEntry &en = tab->e[find_entry(tab, lo, n, item)];
         const ServeReqDev &r = reqs[en.slot];
@@ -190,17 +204,17 @@ __global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *_
             const int l = static_cast<int>(en.level);
             uint32_t *red = reinterpret_cast<uint32_t *>(lds);
             if (r.precision == COS_FP64)
-                serve_level<double, false>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<double, false, KIND>(r, l, local, en.n_rg, red, wave, lane);
             else if (r.precision == COS_FP32_RESCALED)
-                serve_level<float, true>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<float, true, KIND>(r, l, local, en.n_rg, red, wave, lane);
             else
-                serve_level<float, false>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<float, false, KIND>(r, l, local, en.n_rg, red, wave, lane);
         } else if (kind == SK_FINAL) {
             double *red = reinterpret_cast<double *>(lds);
             if (r.precision == COS_FP64)
-                serve_final<double>(r, local, red, wave, lane);
+                serve_final<double, KIND>(r, local, red, wave, lane);
             else
-                serve_final<float>(r, local, red, wave, lane);
+                serve_final<float, KIND>(r, local, red, wave, lane);
         } else {  // SK_COMBINE
             const int64_t s = static_cast<int64_t>(local) * kServeCombineTile + threadIdx.x;
             if (s < r.S)
@@ -216,12 +230,23 @@ __global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *_
 
 }  // namespace
 
+namespace {
+
+template <typename Kern>
+hipError_t allow_full_lds(Kern kern) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(kLdsBytes));
+}
+
+}  // namespace
+
 hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, const ServeReqDev *d_reqs,
-                                  hipGraphExec_t *exec) {
+                                  bool with_lookup, hipGraphExec_t *exec) {
     static std::atomic<bool> attr_set{false};
     if (!attr_set.load(std::memory_order_acquire)) {
-        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(serve_fused_kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsBytes));
+        hipError_t err = allow_full_lds(serve_fused_kernel<FK_RATIONAL, SS_FUSED>);
+        if (err == hipSuccess)
+            err = allow_full_lds(serve_fused_kernel<FK_LOOKUP, SS_FUSED_LOOKUP>);
         if (err != hipSuccess)
             return err;
         attr_set.store(true, std::memory_order_release);
@@ -230,29 +255,29 @@ hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, cons
     hipError_t err = hipGraphCreate(&graph, 0);
     if (err != hipSuccess)
         return err;
-    hipGraphNode_t upload = nullptr, fused = nullptr, stream = nullptr;
+    hipGraphNode_t upload = nullptr;
     err = hipGraphAddMemcpyNode1D(&upload, graph, nullptr, 0, d_tab, h_tab, sizeof(StepTable),
                                   hipMemcpyHostToDevice);
     const StepTable *tab_arg = d_tab;
     const ServeReqDev *reqs_arg = d_reqs;
     void *args[] = {&tab_arg, &reqs_arg};
-    if (err == hipSuccess) {
+    auto add = [&](void *func, bool fused) {
+        if (err != hipSuccess)
+            return;
         hipKernelNodeParams kp{};
-        kp.func = reinterpret_cast<void *>(serve_fused_kernel);
-        kp.gridDim = dim3(kServeFusedGrid);
-        kp.blockDim = dim3(kFusedThreads);
-        kp.sharedMemBytes = static_cast<unsigned>(kLdsBytes);
+        kp.func = func;
+        kp.gridDim = dim3(fused ? kServeFusedGrid : kServeStreamGrid);
+        kp.blockDim = dim3(fused ? kFusedThreads : kBlock);
+        kp.sharedMemBytes = fused ? static_cast<unsigned>(kLdsBytes) : 0u;
         kp.kernelParams = args;
-        err = hipGraphAddKernelNode(&fused, graph, &upload, 1, &kp);
-    }
-    if (err == hipSuccess) {
-        hipKernelNodeParams kp{};
-        kp.func = reinterpret_cast<void *>(serve_stream_kernel);
-        kp.gridDim = dim3(kServeStreamGrid);
-        kp.blockDim = dim3(kBlock);
-        kp.sharedMemBytes = 0;
-        kp.kernelParams = args;
-        err = hipGraphAddKernelNode(&stream, graph, &upload, 1, &kp);
+        hipGraphNode_t node = nullptr;
+        err = hipGraphAddKernelNode(&node, graph, &upload, 1, &kp);
+    };
+    add(reinterpret_cast<void *>(serve_fused_kernel<FK_RATIONAL, SS_FUSED>), true);
+    add(reinterpret_cast<void *>(serve_stream_kernel<FK_RATIONAL, SS_STREAMED>), false);
+    if (with_lookup) {
+        add(reinterpret_cast<void *>(serve_fused_kernel<FK_LOOKUP, SS_FUSED_LOOKUP>), true);
+        add(reinterpret_cast<void *>(serve_stream_kernel<FK_LOOKUP, SS_STREAMED_LOOKUP>), false);
     }
     if (err == hipSuccess)
         err = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);

@@ -97,16 +97,16 @@ std::vector<Req *> admit(std::deque<Req *> &queue, std::vector<Req *> &slots, Ar
 }
 
 // Compose one step: every active request with a stage left contributes its
-// next stage, whole-graph (fused) requests first, then the streamed ones,
-// each section in slot order; emit(section, request) is called for each in
-// that order, and the request's next_stage advances.  Returns how many
-// requests the step holds.  Req needs: fused, next_stage, n_stages.
+// next stage, grouped by section (0 .. n_sections-1, each run by its own
+// kernel), each section in slot order; emit(section, request) is called for
+// each in that order, and the request's next_stage advances.  Returns how
+// many requests the step holds.  Req needs: section, next_stage, n_stages.
 template <class Req, class Emit>
-int compose_step(const std::vector<Req *> &slots, Emit emit) {
+int compose_step(const std::vector<Req *> &slots, int n_sections, Emit emit) {
     int n = 0;
-    for (int section = 0; section < 2; ++section)
+    for (int section = 0; section < n_sections; ++section)
         for (Req *r : slots) {
-            if (!r || r->next_stage >= r->n_stages || r->fused != (section == 0))
+            if (!r || r->next_stage >= r->n_stages || r->section != section)
                 continue;
             emit(section, r);
             ++r->next_stage;

@@ -26,6 +26,7 @@ struct ServeReqDev {
     const int32_t *row_ptr;
     const EdgeRec *edges;
     const EdgeRec32 *edges32;
+    const EdgeRecL *edgesL;   // lookup factors (x is then the sample's table, [n_slots][S])
     const LevelDev *levels;
     const double *x;
     double *out;
@@ -51,20 +52,31 @@ struct StepEntry {
     uint32_t pad[2];
 };
 
-// Entries [0, n_fused) are whole-graph (fused) work, entries
-// [n_fused, n_fused + n_streamed) level / final / combine work; each section
-// numbers its items from 0.
+// Sections of a step, each run by its own kernel: whole-graph (fused) work and
+// level / final / combine (streamed) work, for rational and for lookup
+// factors.  Entries are stored section by section; each section numbers its
+// items from 0.
+enum ServeSection : uint32_t { SS_FUSED = 0, SS_STREAMED = 1, SS_FUSED_LOOKUP = 2, SS_STREAMED_LOOKUP = 3,
+                               SS_COUNT = 4 };
+
 struct StepTable {
-    uint32_t n_fused, items_fused;
-    uint32_t n_streamed, items_streamed;
-    uint32_t pad[4];
+    uint32_t n[SS_COUNT];      // entries per section
+    uint32_t items[SS_COUNT];  // items per section
     StepEntry e[kServeMaxEntries];
 };
+// First entry of section sec.
+__host__ __device__ inline uint32_t section_begin(const StepTable &t, uint32_t sec) {
+    uint32_t b = 0;
+    for (uint32_t i = 0; i < sec; ++i)
+        b += t.n[i];
+    return b;
+}
 
 // Build the executable graph of one step: upload of the host table h_tab to
-// d_tab, then the fused-work and streamed-work kernels as two independent
-// branches reading d_tab and the slot table d_reqs.
+// d_tab, then one kernel per section as independent branches reading d_tab
+// and the slot table d_reqs -- the two rational-factor sections only
+// (with_lookup false) or all four.
 hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, const ServeReqDev *d_reqs,
-                                  hipGraphExec_t *exec);
+                                  bool with_lookup, hipGraphExec_t *exec);
 
 }  // namespace cosdag

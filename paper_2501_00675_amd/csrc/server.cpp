@@ -41,6 +41,7 @@ struct Request {
     int64_t S = 0;
     cos_precision p = COS_FP64;
     bool fused = false;
+    int section = SS_FUSED;  // ServeSection of its work
     FusedLayout flay;
     Workspace wlay;
     uint64_t footprint = 0, arena_off = 0;
@@ -56,8 +57,10 @@ struct Request {
 struct StepBuf {
     StepTable *h_tab = nullptr;     // pinned
     StepTable *d_tab = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr;         // rational-factor sections
+    hipGraphExec_t exec_lookup = nullptr;  // all four sections
     bool busy = false;
+    bool lookup = false;               // the step has lookup-factor work (replay exec_lookup)
     std::vector<Request *> finishing;  // requests whose last stage is in this step
     cos_step_record rec{};             // the step's trace record (t_done_ns set on completion)
     struct Server *srv = nullptr;
@@ -172,6 +175,7 @@ hipError_t Server::setup(Request *r) {
     d.row_ptr = g.d_row_ptr;
     d.edges = g.d_edges;
     d.edges32 = g.d_edges32;
+    d.edgesL = g.d_edgesL;
     d.levels = g.d_levels;
     d.x = r->x;
     d.out = r->out;
@@ -254,8 +258,8 @@ void Server::run() {
         if (b && any_stage_left(slots)) {
             // whole-graph (fused) entries first, then level / final / combine entries
             StepTable &t = *b->h_tab;
-            uint32_t n = 0, items[2] = {0, 0}, count[2] = {0, 0};
-            compose_step(slots, [&](int section, Request *r) {
+            uint32_t n = 0, items[SS_COUNT] = {}, count[SS_COUNT] = {};
+            compose_step(slots, SS_COUNT, [&](int section, Request *r) {
                 StepEntry &e = t.e[n++];
                 e.slot = static_cast<uint32_t>(r->slot);
                 e.n_items = stage_items(*r, r->next_stage, &e.n_rg, &e.kind, &e.level);
@@ -268,16 +272,21 @@ void Server::run() {
                 if (r->next_stage + 1 == r->n_stages)
                     b->finishing.push_back(r);
             });
-            t.n_fused = count[0];
-            t.items_fused = items[0];
-            t.n_streamed = count[1];
-            t.items_streamed = items[1];
-            b->rec = cos_step_record{st.steps, now_ns(), 0, static_cast<int32_t>(count[0]),
-                                     static_cast<int32_t>(count[1]), static_cast<int64_t>(items[0]) + items[1]};
+            int64_t all_items = 0;
+            for (int sec = 0; sec < SS_COUNT; ++sec) {
+                t.n[sec] = count[sec];
+                t.items[sec] = items[sec];
+                all_items += items[sec];
+            }
+            b->lookup = count[SS_FUSED_LOOKUP] + count[SS_STREAMED_LOOKUP] > 0;
+            b->rec = cos_step_record{st.steps, now_ns(), 0,
+                                     static_cast<int32_t>(count[SS_FUSED] + count[SS_FUSED_LOOKUP]),
+                                     static_cast<int32_t>(count[SS_STREAMED] + count[SS_STREAMED_LOOKUP]),
+                                     all_items};
             b->busy = true;
             ++inflight;
             ++st.steps;
-            st.items += items[0] + items[1];
+            st.items += all_items;
             st.max_step_requests = std::max<int64_t>(st.max_step_requests, n);
         } else {
             b = nullptr;
@@ -302,7 +311,7 @@ void Server::run() {
         hipError_t err = hipSuccess;
         {
             TimedLaunch tl(KK_SERVE, stream);
-            err = hipGraphLaunch(b->exec, stream);
+            err = hipGraphLaunch(b->lookup ? b->exec_lookup : b->exec, stream);
         }
         if (err == hipSuccess)
             err = hipLaunchHostFunc(stream, step_done, b);
@@ -324,6 +333,8 @@ Server::~Server() {
     for (StepBuf &b : bufs) {
         if (b.exec)
             (void)hipGraphExecDestroy(b.exec);
+        if (b.exec_lookup)
+            (void)hipGraphExecDestroy(b.exec_lookup);
         if (b.d_tab)
             (void)hipFree(b.d_tab);
         if (b.h_tab)
@@ -376,7 +387,9 @@ extern "C" cos_status cos_server_create(uint64_t hbm_budget, int32_t max_slots, 
             if (err == hipSuccess)
                 err = hipMalloc(reinterpret_cast<void **>(&b.d_tab), sizeof(StepTable));
             if (err == hipSuccess)
-                err = serve_build_step_graph(b.d_tab, b.h_tab, s->d_reqs, &b.exec);
+                err = serve_build_step_graph(b.d_tab, b.h_tab, s->d_reqs, false, &b.exec);
+            if (err == hipSuccess)
+                err = serve_build_step_graph(b.d_tab, b.h_tab, s->d_reqs, true, &b.exec_lookup);
         }
         if (err != hipSuccess)
             return hip_fail(err, "cos_server_create");
@@ -398,8 +411,6 @@ extern "C" cos_status cos_server_add_graph(cos_server *h, const cos_graph *g, in
     const Graph &G = graph_of(g);
     if (G.device != s->device)
         return fail(COS_EINVAL, "cos_server_add_graph: graph lives on another device");
-    if (G.kind != FK_RATIONAL)
-        return fail(COS_EINVAL, "cos_server_add_graph: graphs with lookup factors are evaluated with cos_evaluate");
     std::lock_guard<std::mutex> lk(s->mu);
     s->graphs.push_back(&G);
     *gid = static_cast<int32_t>(s->graphs.size() - 1);
@@ -432,6 +443,7 @@ extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double
     r->p = p;
     // the same plan choice cos_evaluate makes for this graph (results are bit-identical to it)
     r->fused = g.path == COS_PATH_FUSED || (g.path == COS_PATH_AUTO && fused_fits(g, p));
+    r->section = (r->fused ? SS_FUSED : SS_STREAMED) + (g.kind == FK_LOOKUP ? SS_FUSED_LOOKUP : 0);
     if (r->fused) {
         if (!fused_fits(g, p))
             return fail(COS_EINVAL, "cos_server_submit: fused plan requested but the graph does not fit in LDS");

@@ -60,13 +60,17 @@ class Server:
                out_exp: torch.Tensor | None = None, sync_inputs: bool = True) -> Ticket:
         """Queue a request; returns its ticket (with .out and .out_exp).
 
-        x: float64[3, S] on the device.  The server reads x on its own stream,
-        so x must be complete when the request is admitted: with sync_inputs
-        the current torch stream is synchronised first.
+        x: float64[R, S] on the device, R = 3 (coordinates) for rational factors
+        or n_slots (each sample's table) for lookup factors.  The server reads
+        x on its own stream, so x must be complete when the request is
+        admitted: with sync_inputs the current torch stream is synchronised
+        first.
         """
+        # the row count of the graph's input (an unknown id is left for the library to refuse)
+        rows = self._graphs[int(gid)].n_inputs if 0 <= int(gid) < len(self._graphs) else x.shape[0]
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 2
-                and x.shape[0] == 3 and x.is_contiguous()):
-            raise ValueError("x must be a contiguous float64 CUDA tensor of shape [3, S]")
+                and x.shape[0] == rows and x.is_contiguous()):
+            raise ValueError(f"x must be a contiguous float64 CUDA tensor of shape [{rows}, S]")
         S = x.shape[1]
         if out is None:
             out = torch.empty(S, dtype=torch.float64, device=x.device)

@@ -4,7 +4,7 @@ tests/host/sched_check.cpp is compiled with the system C++ compiler against
 the library's own scheduling header and run: random streams of requests are
 admitted by slot and workspace, stepped stage by stage and retired or
 cancelled, and every step checks queue order, arena accounting (no overlap,
-coalescing), slot use, one stage per request per step, fused-first step
+coalescing), slot use, one stage per request per step, section-ordered step
 layout and that each request ends after exactly its stage count.
 """
 

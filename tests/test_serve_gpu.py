@@ -110,6 +110,43 @@ def test_mix_bit_identical_to_evaluate_and_alone(P):
         assert_parity(outs[i][idx], V, Q, j["precision"], f"mix request {i}")
 
 
+def test_lookup_graphs_served_bit_identical_alone_and_mixed(P):
+    # lookup-factor graphs (a narrow one on the fused plan, a wide one streamed) share steps
+    # with a rational graph; every result must equal cos_evaluate's bits
+    graphs = [make_config("mid", S=1500, factor="lookup", width=200, L=6, degree=3, seed=31),
+              make_config("mid", S=1300, factor="lookup", width=900, L=5, degree=3, seed=32),
+              make_config("mid", S=1200, width=700, L=5, degree=3, seed=33)]
+    Gs = [P.Graph.from_leveled(g) for g, _ in graphs]
+    code = {"fp64": 0, "fp32r": 1, "fp32": 2}
+    assert (Gs[0].info()["fused_mask"] >> code["fp64"]) & 1 and not Gs[1].info()["fused_mask"]
+    jobs = [(gi, p) for p in ("fp64", "fp32r", "fp32") for gi in range(3)]
+    xs = [to_dev(graphs[gi][1]) for gi, _ in jobs]
+    refs = [gpu_eval(Gs[gi], graphs[gi][1], p) for gi, p in jobs]
+    torch.cuda.synchronize()
+    say(f"serve lookup mix: {len(jobs)} requests")
+    with P.Server(512 * MiB, 16) as srv:
+        gids = [srv.add_graph(G) for G in Gs]
+        tickets = [srv.submit(gids[gi], x, p, sync_inputs=False) for (gi, p), x in zip(jobs, xs)]
+        stats = [srv.wait(t) for t in tickets]
+        s = srv.stats()
+    assert all(st["status"] == 0 for st in stats) and s["max_step_requests"] > 1
+    for i, (t, r) in enumerate(zip(tickets, refs)):
+        assert np.array_equal(bits(t.out.cpu().numpy()), bits(r)), f"request {i} {jobs[i]}"
+    # alone, and against the oracle on sampled outputs
+    with P.Server(512 * MiB, 4) as srv:
+        gid = srv.add_graph(Gs[1])
+        t = srv.submit(gid, xs[1], "fp64")
+        srv.wait(t)
+        assert np.array_equal(bits(t.out.cpu().numpy()), bits(refs[1]))
+        with pytest.raises(ValueError):
+            srv.submit(gid, to_dev(graphs[2][1]), "fp64")  # coordinates where a table is due
+    for i, (gi, p) in enumerate(jobs):
+        g, x = graphs[gi]
+        idx = sample_subset(x.shape[1], 48, seed=i)
+        V, Q = oracle_ref(g, x, idx)
+        assert_parity(tickets[i].out.cpu().numpy()[idx], V, Q, p, f"lookup mix {i}")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32r"])
 def test_admission_waits_for_budget(P, precision):
     g, x = make_config("mid", S=2000, width=700, L=5, degree=3)
