@@ -560,8 +560,9 @@ def main():
         calibrate_copy(args.steps)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the path shards over samples with no "
-                                   "per-level exchange (see the design notes), but no multi-GPU run is provided",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: samples are independent, so the path "
+                                   "would replicate the graph on every GPU and give each S/N samples with no "
+                                   "per-level exchange, but no multi-GPU run is provided",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
