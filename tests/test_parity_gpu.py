@@ -118,6 +118,21 @@ def test_large_full_size_sampled(P):
         assert_parity(y[idx], V, Q, precision, "large")
 
 
+@pytest.mark.slow
+def test_large_graph_beyond_one_sweep_is_chunked(P):
+    # the large graph's level buffer for 4500 samples (65536 rows x 4608 x 8 B) exceeds the 2 GiB a sweep
+    # addresses with 32-bit offsets: the library sweeps 3840 samples, then the remaining 660
+    g, x = make_config("large", S=4500, seed=17)
+    G = graph(P, g)
+    assert G.workspace_bytes(4500, "fp64") < 2 * 65536 * 4608 * 8  # the plan is a chunk, not the whole S
+    idx = np.unique(np.concatenate([sample_subset(4500, 14, seed=3), [3839, 3840, 4499]]))
+    V, Q = oracle_ref(g, x, idx)
+    for precision in ("fp64", "fp32r"):
+        say(f"large S=4500 {precision}")
+        y = gpu_eval(G, x, precision)
+        assert_parity(y[idx], V, Q, precision, "large chunked")
+
+
 @pytest.mark.parametrize("name,expect", [("tiny", 12), ("mid", 2 ** 28), ("precision", 2 ** 78)])
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_all_ones_path_counts_exact(P, name, expect, precision):
