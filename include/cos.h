@@ -225,9 +225,11 @@ cos_status cos_evaluate_workspace_size(const cos_graph *g, int64_t S, cos_precis
  *                (hipMallocAsync / hipFreeAsync).
  *   stream       hipStream_t as void*.
  *
- * Asynchronous: returns once the work is queued.  Errors: COS_EINVAL (NULL or
- * misaligned pointers, bad S or precision, workspace too small), COS_ENOMEM,
- * COS_EDEVICE (launch failure).
+ * Asynchronous: returns once the work is queued.  With a workspace it queues
+ * kernel launches only (no allocation, no memset), so it may be captured into
+ * a HIP graph on `stream` and replayed; replays read x and write out afresh.
+ * Errors: COS_EINVAL (NULL or misaligned pointers, bad S or precision,
+ * workspace too small), COS_ENOMEM, COS_EDEVICE (launch failure).
  */
 cos_status cos_evaluate(const cos_graph *g, const double *x_dev, int64_t S, cos_precision p,
                         double *out_dev, int32_t *out_exp_dev, void *workspace_dev,

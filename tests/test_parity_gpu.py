@@ -340,3 +340,34 @@ def test_timing_probe_counts_launches(P):
     assert n_l == g.L - 1 and ms_l > 0
     assert n_p == 1 and ms_p > 0
     assert n_f == 1 and ms_f > 0
+
+
+@pytest.mark.parametrize("name,precision", [("mid", "fp64"), ("mid", "fp32r"), ("precision", "fp16r"),
+                                            ("precision", "fp32r")])
+def test_evaluate_captured_in_a_graph_replays_bit_identical(P, name, precision):
+    # cos_evaluate with a caller workspace issues kernels only (no allocation, no memset), so it
+    # can be captured in a HIP graph; every replay, with new samples written in between, must
+    # give the eager result's bits
+    g, x = make_config(name, S=2048)
+    G = graph(P, g)
+    rng = np.random.default_rng(5)
+    xs = [x] + [x + rng.normal(0, 0.05, x.shape) for _ in range(3)]
+    eager = [gpu_eval(G, xi, precision) for xi in xs]
+    xd = to_dev(xs[0])
+    out = torch.empty(x.shape[1], dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(G.workspace_bytes(x.shape[1], precision), dtype=torch.uint8, device="cuda:0")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        G.evaluate(xd, precision, out=out, workspace=ws, stream=s)  # warm-up outside the capture
+    s.synchronize()
+    graph_ = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph_, stream=s):
+        G.evaluate(xd, precision, out=out, workspace=ws, stream=s)
+    for i in (1, 2, 0, 3):
+        xd.copy_(to_dev(xs[i]))
+        torch.cuda.synchronize()
+        graph_.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager[i]), f"replay with samples {i}"
+        gpu_eval(G, xs[(i + 1) % 4], precision)  # eager work between replays
