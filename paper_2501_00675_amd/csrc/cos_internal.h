@@ -60,6 +60,9 @@ static_assert(sizeof(EdgeRecL) == 32, "EdgeRecL layout");
 
 // Edge-factor kinds (cos_graph_info.factor_kind).
 enum FactorKind : int32_t { FK_RATIONAL = 0, FK_LOOKUP = 1 };
+// Kernel-only kind: lookup factors whose interior levels read a binary32 copy
+// of the sample tables (the binary32 paths of cos_evaluate).
+constexpr int32_t FK_LOOKUP_T32 = 2;
 
 // Per edge level l = 1..L (stored at index l-1).
 struct LevelDesc {
@@ -160,14 +163,22 @@ constexpr int32_t kMaxHeadroom16 = 96;
 struct Workspace {
     size_t bytes = 0;
     size_t off_buf0 = 0, off_buf1 = 0, off_maxbits = 0, off_partial = 0;
+    size_t off_table32 = 0;    // binary32 sample tables [n_slots][S_pad] (lookup, binary32 paths), if used
+    bool table32 = false;
     int64_t S_chunk = 0;       // samples per sweep
     int64_t S_pad = 0;         // row length of the level buffers
     int32_t final_chunks = 0;  // partial sums of the final node
     bool fused = false;        // whole sweep in the LDS-resident kernel
 };
 constexpr int64_t kMaxLevelBytes = int64_t(1) << 31;
-// Layout for sweeps of at most S_chunk samples (S_chunk > 0).
-Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p);
+// Whether the sweep of a graph at precision p reads binary32 copies of the
+// sample tables (lookup factors, binary32 arithmetic).
+inline bool uses_table32(const Graph &g, cos_precision p) {
+    return g.kind == FK_LOOKUP && (p == COS_FP32 || p == COS_FP32_RESCALED || p == COS_BF16_RESCALED);
+}
+// Layout for sweeps of at most S_chunk samples (S_chunk > 0); with_table32
+// false leaves out the binary32 tables (the serving runtime reads binary64 ones).
+Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p, bool with_table32 = true);
 // Natural plan for S samples: fused if it fits, else the largest chunk allowed.
 Workspace plan_workspace(const Graph &g, int64_t S, cos_precision p);
 // Largest sample chunk whose level buffer stays below kMaxLevelBytes.
@@ -177,9 +188,14 @@ int64_t max_chunk(const Graph &g, cos_precision p);
 // the chunk's first sample; xs is the distance between coordinate rows of x.
 // Rescaled precisions: prev_max / cur_max are the maxbits rows l-1 and l,
 // h_next the headroom exponent folded into cur_max (0 unless binary16).
+// t32 (nullable): binary32 sample tables [n_slots][ld] of a lookup graph,
+// read instead of x by the interior levels.
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur,
                         int64_t ld, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
-                        uint32_t *cur_max, int32_t h_next, hipStream_t s);
+                        uint32_t *cur_max, int32_t h_next, hipStream_t s, const float *t32 = nullptr);
+// t32[i][s] = fl32(x[i][s]) for s < S, 0 for S <= s < ld (n rows).
+hipError_t launch_table32(const double *x, int64_t xs, int64_t S, int32_t n, float *t32, int64_t ld,
+                          hipStream_t s);
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld,
                         const double *x, int64_t S, int64_t xs, const uint32_t *maxbits, double *partial,
                         int32_t chunks, double *out, int32_t *out_exp, hipStream_t s);
@@ -200,7 +216,8 @@ struct McArgs {
 // runs every step of the walkers instead (rational factors).
 bool fused_fits(const Graph &g, cos_precision p);
 hipError_t launch_fused(const Graph &g, cos_precision p, const double *x, int64_t S, double *out,
-                        int32_t *out_exp, hipStream_t s, const McArgs *mc = nullptr);
+                        int32_t *out_exp, hipStream_t s, const McArgs *mc = nullptr, const float *t32 = nullptr,
+                        int64_t ld32 = 0);
 
 int32_t final_chunk_count(int64_t final_in_degree);
 

@@ -18,7 +18,7 @@ int64_t max_chunk(const Graph &g, cos_precision p) {
     return cap / kSamplePad * kSamplePad;
 }
 
-Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p) {
+Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p, bool with_table32) {
     Workspace w;
     w.S_chunk = S_chunk;
     w.S_pad = round_up(std::max<int64_t>(S_chunk, 1), kSamplePad);
@@ -34,6 +34,9 @@ Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p) {
     w.off_maxbits = is_rescaled(p) ? take(static_cast<size_t>(g.L + 1) * w.S_pad * sizeof(uint32_t)) : 0;
     w.final_chunks = final_chunk_count(g.levels.back().n_edges);
     w.off_partial = take(static_cast<size_t>(w.final_chunks) * w.S_pad * sizeof(double));
+    w.table32 = with_table32 && uses_table32(g, p);
+    if (w.table32)
+        w.off_table32 = take(static_cast<size_t>(g.n_slots) * w.S_pad * sizeof(float));
     w.bytes = std::max<size_t>(off, 256);
     return w;
 }
@@ -41,9 +44,12 @@ Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p) {
 Workspace plan_workspace(const Graph &g, int64_t S, cos_precision p) {
     Workspace w;
     w.fused = g.path == COS_PATH_FUSED || (g.path == COS_PATH_AUTO && fused_fits(g, p));
-    if (w.fused) {  // levels live in LDS: no device scratch
+    if (w.fused) {  // levels live in LDS: device scratch only for binary32 tables
         w.S_chunk = S;
-        w.bytes = 256;
+        w.S_pad = round_up(std::max<int64_t>(S, 1), kSamplePad);
+        w.table32 = uses_table32(g, p);
+        const size_t t32 = w.table32 ? static_cast<size_t>(g.n_slots) * w.S_pad * sizeof(float) : 0;
+        w.bytes = std::max<size_t>(static_cast<size_t>(round_up(static_cast<int64_t>(t32), 256)), 256);
         return w;
     }
     const int64_t cap = max_chunk(g, p);
@@ -71,11 +77,15 @@ hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char
     void *bufs[2] = {base + w.off_buf0, base + w.off_buf1};
     uint32_t *maxbits = is_rescaled(p) ? reinterpret_cast<uint32_t *>(base + w.off_maxbits) : nullptr;
     double *partial = reinterpret_cast<double *>(base + w.off_partial);
+    float *t32 = w.table32 ? reinterpret_cast<float *>(base + w.off_table32) : nullptr;
     hipError_t err = hipSuccess;
+    // lookup factors at binary32: the chunk's tables rounded once, read by the interior levels
+    if (t32)
+        err = launch_table32(x, xs, S, g.n_slots, t32, w.S_pad, st);
     // row 0: the root's value 1 times level 1's headroom 2^h (0 = no shift);
     // rows 1..L: zero, for the atomic max of each level
     const int32_t h1 = g.L >= 2 ? headroom(g, p, 1) : 0;
-    if (maxbits)
+    if (maxbits && err == hipSuccess)
         err = launch_fill_u32(maxbits, h1 ? static_cast<uint32_t>(127 + h1) << 23 : 0u, w.S_pad, st);
     if (maxbits && err == hipSuccess)
         err = launch_fill_u32(maxbits + w.S_pad, 0u, static_cast<int64_t>(g.L) * w.S_pad, st);
@@ -85,7 +95,7 @@ hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char
         const uint32_t *pm = maxbits ? maxbits + static_cast<int64_t>(l - 1) * w.S_pad : nullptr;
         uint32_t *cm = (maxbits && l <= g.L - 2) ? maxbits + static_cast<int64_t>(l) * w.S_pad : nullptr;
         const int32_t h_next = l <= g.L - 2 ? headroom(g, p, l + 1) : 0;
-        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st);
+        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st, t32);
         prev = cur;
     }
     if (err == hipSuccess)
@@ -158,7 +168,11 @@ extern "C" cos_status cos_evaluate(const cos_graph *h, const double *x_dev, int6
 
     hipError_t err = hipSuccess;
     if (w.fused) {
-        err = launch_fused(g, p, x_dev, S, out_dev, out_exp_dev, st);
+        float *t32 = w.table32 ? static_cast<float *>(ws) : nullptr;
+        if (t32)
+            err = launch_table32(x_dev, S, S, g.n_slots, t32, w.S_pad, st);
+        if (err == hipSuccess)
+            err = launch_fused(g, p, x_dev, S, out_dev, out_exp_dev, st, nullptr, t32, w.S_pad);
     } else {
         for (int64_t s0 = 0; s0 < S && err == hipSuccess; s0 += w.S_chunk) {
             const int64_t n = std::min(w.S_chunk, S - s0);

@@ -47,14 +47,16 @@ inline FusedLayout fused_layout(const Graph &g, size_t elem, bool rescale, int K
     return f;
 }
 
-// Lookup factors read each sample's table (n_slots binary64 entries) for
+// Lookup factors read each sample's table (n_slots entries) for
 // every edge; the tables of the tiles resident on one XCD (one workgroup per
 // CU, 32 CUs) should stay within half of its 4 MiB L2, else the entries are
 // fetched again from the Infinity Cache on every edge.
 constexpr int64_t kLookupL2Budget = int64_t(2) << 20;
-inline bool lookup_tables_fit(const Graph &g, int K) {
+// entry: bytes of a table entry as the interior levels read it (binary32
+// paths read a binary32 copy of the tables).
+inline bool lookup_tables_fit(const Graph &g, int K, size_t entry) {
     return g.kind != FK_LOOKUP ||
-           static_cast<int64_t>(g.n_slots) * kWave * K * static_cast<int64_t>(sizeof(double)) * 32 <= kLookupL2Budget;
+           static_cast<int64_t>(g.n_slots) * kWave * K * static_cast<int64_t>(entry) * 32 <= kLookupL2Budget;
 }
 
 // Largest samples-per-lane K in {4, 2, 1} whose accumulators fit in registers
@@ -72,7 +74,7 @@ inline int fused_k(const Graph &g, cos_precision p) {
     const size_t elem = p == COS_FP64 ? sizeof(double) : sizeof(float);
     for (int K : {4, 2, 1})
         if (acc_fits(elem, K, rmax) && fused_layout(g, elem, p == COS_FP32_RESCALED, K).total <= kLdsBytes &&
-            (K == 1 || lookup_tables_fit(g, K)))
+            (K == 1 || lookup_tables_fit(g, K, elem)))
             return K;
     return 0;
 }

@@ -76,7 +76,7 @@ hipError_t allow_full_lds(Kern kern, std::atomic<bool> &attr_set) {
 // mc: NULL for a sweep of x into out; else a whole walker run (rational factors).
 template <typename T, int K, int RMAX, bool RESCALE, int KIND>
 hipError_t launch_fused_t(const Graph &g, const double *x, int64_t S, double *out, int32_t *out_exp, hipStream_t s,
-                          const McArgs *mc) {
+                          const McArgs *mc, const float *t32, int64_t ld32) {
     if constexpr (!acc_fits(sizeof(T), K, RMAX)) {
         return hipErrorInvalidValue;  // never selected by fused_k
     } else {
@@ -104,7 +104,8 @@ hipError_t launch_fused_t(const Graph &g, const double *x, int64_t S, double *ou
         hipError_t err = allow_full_lds(kern, attr_set);
         if (err != hipSuccess)
             return err;
-        const FusedGraph G{g.d_row_ptr, g.d_edges, g.d_edges32, g.d_edgesL, g.d_levels, g.L, x, S, out, out_exp};
+        const FusedGraph G{g.d_row_ptr, g.d_edges, g.d_edges32, g.d_edgesL, g.d_levels, g.L, x, S, out, out_exp,
+                           t32, ld32};
         TimedLaunch tl(KK_FUSED, s);
         hipLaunchKernelGGL(kern, grid, dim3(kFusedThreads), f.total, s, G, static_cast<uint32_t>(f.off_red),
                            static_cast<uint32_t>(f.off_part));
@@ -114,40 +115,45 @@ hipError_t launch_fused_t(const Graph &g, const double *x, int64_t S, double *ou
 
 template <typename T, int K, bool RESCALE, int KIND>
 hipError_t dispatch_rows(const Graph &g, const double *x, int64_t S, double *out, int32_t *out_exp, hipStream_t s,
-                         const McArgs *mc) {
+                         const McArgs *mc, const float *t32, int64_t ld32) {
     switch (rows_variant((g.max_width + kFusedWaves - 1) / kFusedWaves)) {
     case 2:
-        return launch_fused_t<T, K, 2, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return launch_fused_t<T, K, 2, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
     case 4:
-        return launch_fused_t<T, K, 4, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return launch_fused_t<T, K, 4, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
     case 8:
-        return launch_fused_t<T, K, 8, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return launch_fused_t<T, K, 8, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
     case 16:
-        return launch_fused_t<T, K, 16, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return launch_fused_t<T, K, 16, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
     case 24:
-        return launch_fused_t<T, K, 24, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return launch_fused_t<T, K, 24, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
     case kMaxRows:
-        return launch_fused_t<T, K, kMaxRows, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return launch_fused_t<T, K, kMaxRows, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T, bool RESCALE, int KIND>
 hipError_t dispatch_k(const Graph &g, int K, const double *x, int64_t S, double *out, int32_t *out_exp,
-                      hipStream_t s, const McArgs *mc) {
+                      hipStream_t s, const McArgs *mc, const float *t32, int64_t ld32) {
     if (K == 4)
-        return dispatch_rows<T, 4, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return dispatch_rows<T, 4, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
     if (K == 2)
-        return dispatch_rows<T, 2, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
-    return dispatch_rows<T, 1, RESCALE, KIND>(g, x, S, out, out_exp, s, mc);
+        return dispatch_rows<T, 2, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
+    return dispatch_rows<T, 1, RESCALE, KIND>(g, x, S, out, out_exp, s, mc, t32, ld32);
 }
 
 template <typename T, bool RESCALE>
 hipError_t dispatch_kind(const Graph &g, int K, const double *x, int64_t S, double *out, int32_t *out_exp,
-                         hipStream_t s, const McArgs *mc) {
-    if (g.kind == FK_LOOKUP)
-        return dispatch_k<T, RESCALE, FK_LOOKUP>(g, K, x, S, out, out_exp, s, mc);
-    return dispatch_k<T, RESCALE, FK_RATIONAL>(g, K, x, S, out, out_exp, s, mc);
+                         hipStream_t s, const McArgs *mc, const float *t32, int64_t ld32) {
+    if (g.kind == FK_LOOKUP) {
+        if constexpr (sizeof(T) == sizeof(float)) {
+            if (t32)
+                return dispatch_k<T, RESCALE, FK_LOOKUP_T32>(g, K, x, S, out, out_exp, s, mc, t32, ld32);
+        }
+        return dispatch_k<T, RESCALE, FK_LOOKUP>(g, K, x, S, out, out_exp, s, mc, t32, ld32);
+    }
+    return dispatch_k<T, RESCALE, FK_RATIONAL>(g, K, x, S, out, out_exp, s, mc, t32, ld32);
 }
 
 }  // namespace
@@ -155,7 +161,7 @@ hipError_t dispatch_kind(const Graph &g, int K, const double *x, int64_t S, doub
 bool fused_fits(const Graph &g, cos_precision p) { return fused_k(g, p) > 0; }
 
 hipError_t launch_fused(const Graph &g, cos_precision p, const double *x, int64_t S, double *out, int32_t *out_exp,
-                        hipStream_t s, const McArgs *mc) {
+                        hipStream_t s, const McArgs *mc, const float *t32, int64_t ld32) {
     int K = fused_k(g, p);
     if (K == 0)
         return hipErrorInvalidValue;
@@ -165,11 +171,11 @@ hipError_t launch_fused(const Graph &g, cos_precision p, const double *x, int64_
         K = std::min(K, 2);
     switch (p) {
     case COS_FP64:
-        return dispatch_kind<double, false>(g, K, x, S, out, out_exp, s, mc);
+        return dispatch_kind<double, false>(g, K, x, S, out, out_exp, s, mc, t32, ld32);
     case COS_FP32_RESCALED:
-        return dispatch_kind<float, true>(g, K, x, S, out, out_exp, s, mc);
+        return dispatch_kind<float, true>(g, K, x, S, out, out_exp, s, mc, t32, ld32);
     case COS_FP32:
-        return dispatch_kind<float, false>(g, K, x, S, out, out_exp, s, mc);
+        return dispatch_kind<float, false>(g, K, x, S, out, out_exp, s, mc, t32, ld32);
     default:
         return hipErrorInvalidValue;
     }

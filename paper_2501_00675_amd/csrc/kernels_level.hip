@@ -70,7 +70,7 @@ template <typename T, int K, int ROWS, bool FROM_ROOT, bool RESCALE, int KIND, t
 __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     const int32_t *__restrict__ row_ptr, const typename SweepPath<T, KIND>::Rec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
     int32_t n_tiles, int32_t xcd_group, int32_t reverse_tiles, const V *__restrict__ prev, V *__restrict__ cur, int64_t ld,
-    const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
+    const SampleElem<KIND> *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
     uint32_t *__restrict__ cur_max, int32_t h_next) {
     int tile, rg;
     if (!block_tile(n_rg, n_tiles, xcd_group, reverse_tiles, tile, rg))
@@ -166,10 +166,20 @@ int level_k(int64_t w_src) {
     return fits(2) ? 2 : 4;
 }
 
+// KIND FK_LOOKUP_T32 reads the binary32 tables t32 ([n_slots][ld]) instead of x.
 template <typename T, int K, bool RESCALE, int KIND, typename V>
-hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
-                          int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next,
-                          hipStream_t s) {
+hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x_,
+                          int64_t S, int64_t xs_, const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next,
+                          hipStream_t s, const float *t32) {
+    const SampleElem<KIND> *x;
+    int64_t xs;
+    if constexpr (KIND == FK_LOOKUP_T32) {
+        x = t32;
+        xs = ld;
+    } else {
+        x = x_;
+        xs = xs_;
+    }
     const LevelDesc &d = g.levels[l - 1];
     const int32_t rows_per_group = 4 * kRows;
     const int64_t n_rg = (d.w_dst + rows_per_group - 1) / rows_per_group;
@@ -183,7 +193,7 @@ hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, in
         return hipErrorInvalidConfiguration;
     const int32_t *rp = g.d_row_ptr + d.rp_begin;
     const typename SweepPath<T, KIND>::Rec *recs;
-    if constexpr (KIND == FK_LOOKUP)
+    if constexpr (KIND != FK_RATIONAL)
         recs = g.d_edgesL;
     else if constexpr (sizeof(T) == sizeof(double))
         recs = g.d_edges;
@@ -208,21 +218,28 @@ hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, in
 template <typename T, bool RESCALE, typename V = T, bool LOOKUP_OK = true>
 hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
                           int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next,
-                          hipStream_t s) {
+                          hipStream_t s, const float *t32) {
     const bool k2 = level_k<T, V>(g.levels[l - 1].w_src) == 2;
     if (g.kind == FK_LOOKUP) {
+        if constexpr (!LOOKUP_OK) {
+            return hipErrorInvalidValue;
+        } else if constexpr (sizeof(T) == sizeof(float)) {
+            if (t32)
+                return k2 ? launch_level_k<T, 2, RESCALE, FK_LOOKUP_T32, V>(g, l, prev, cur, ld, x, S, xs, prev_max,
+                                                                            cur_max, h_next, s, t32)
+                          : launch_level_k<T, 4, RESCALE, FK_LOOKUP_T32, V>(g, l, prev, cur, ld, x, S, xs, prev_max,
+                                                                            cur_max, h_next, s, t32);
+        }
         if constexpr (LOOKUP_OK)
             return k2 ? launch_level_k<T, 2, RESCALE, FK_LOOKUP, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                                    h_next, s)
+                                                                    h_next, s, t32)
                       : launch_level_k<T, 4, RESCALE, FK_LOOKUP, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                                    h_next, s);
-        else
-            return hipErrorInvalidValue;
+                                                                    h_next, s, t32);
     }
     return k2 ? launch_level_k<T, 2, RESCALE, FK_RATIONAL, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                              h_next, s)
+                                                              h_next, s, t32)
               : launch_level_k<T, 4, RESCALE, FK_RATIONAL, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                              h_next, s);
+                                                              h_next, s, t32);
 }
 
 }  // namespace
@@ -233,21 +250,47 @@ int32_t final_chunk_count(int64_t final_in_degree) {
 
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
                         const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
-                        int32_t h_next, hipStream_t s) {
+                        int32_t h_next, hipStream_t s, const float *t32) {
     switch (p) {
     case COS_FP64:
-        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s);
+        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s, nullptr);
     case COS_FP32_RESCALED:
-        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s);
+        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s, t32);
     case COS_FP32:
-        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s);
+        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s, t32);
     case COS_FP16_RESCALED:
         return launch_level_t<float, true, _Float16, false>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, h_next,
-                                                            s);
+                                                            s, nullptr);
     case COS_BF16_RESCALED:
-        return launch_level_t<float, true, __bf16>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s);
+        return launch_level_t<float, true, __bf16>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s, t32);
     }
     return hipErrorInvalidValue;
+}
+
+namespace {
+
+// t32[i][s] = fl32(x[i][s]) (nearest even) for s < S, 0 for S <= s < ld.
+__global__ __launch_bounds__(kBlock) void table32_kernel(const double *__restrict__ x, int64_t xs, int64_t S,
+                                                         int32_t n, float *__restrict__ t32, int64_t ld) {
+    const int64_t total = static_cast<int64_t>(n) * ld;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int64_t row = i / ld, s = i - row * ld;
+        t32[i] = s < S ? static_cast<float>(x[row * xs + s]) : 0.0f;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_table32(const double *x, int64_t xs, int64_t S, int32_t n, float *t32, int64_t ld,
+                          hipStream_t s) {
+    const int64_t total = static_cast<int64_t>(n) * ld;
+    if (total <= 0)
+        return hipSuccess;
+    TimedLaunch tl(KK_FILL, s);
+    const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(table32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, x, xs, S, n, t32, ld);
+    return hipGetLastError();
 }
 
 namespace {

@@ -452,7 +452,7 @@ extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double
     } else {
         if (max_chunk(g, p) < S)
             return fail(COS_EINVAL, "cos_server_submit: S too large for one sweep; use cos_evaluate");
-        r->wlay = layout_for_chunk(g, S, p);
+        r->wlay = layout_for_chunk(g, S, p, false);
         r->footprint = r->wlay.bytes;
         r->n_stages = g.L + 1;
         if (r->footprint > s->budget)

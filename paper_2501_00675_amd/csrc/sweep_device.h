@@ -129,6 +129,24 @@ struct LaneTable {
     }
 };
 
+// The same with a binary32 copy of the tables, [slot][ld] with ld >= the
+// padded sample count (padding columns hold 0), so no clamping is needed.
+template <int K>
+struct LaneTable32 {
+    const float *p[K];
+    int64_t ld;
+    __device__ __forceinline__ void load(const float *__restrict__ t, int64_t /*S*/, int64_t lt, int64_t tbase,
+                                         int lane) {
+        ld = lt;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            p[m] = t + tbase + lane + kWave * m;
+    }
+    __device__ __forceinline__ float entry(int32_t slot, int m) const {
+        return p[m][static_cast<int64_t>(slot) * ld];
+    }
+};
+
 template <int K>
 __device__ __forceinline__ double factor(const EdgeRec &e, const LaneSamples<K> &xs, int m) {
     return edge_factor64(e, xs.x0[m], xs.x1[m], xs.x2[m], xs.q[m]);
@@ -144,10 +162,10 @@ __device__ __forceinline__ float factor(const EdgeRec32 &e, const LaneSamples32<
 template <typename T, typename Rec, typename Smp>
 __device__ __forceinline__ T edge_w(const Rec &r, const Smp &xs, int m) {
     if constexpr (std::is_same_v<Rec, EdgeRecL>) {
-        const double t = xs.entry(r.slot, m);
+        const auto t = xs.entry(r.slot, m);
         if constexpr (sizeof(T) == sizeof(double))
             return r.coef * t;
-        else
+        else  // the entry rounded once to binary32 (here or when the binary32 table was made)
             return r.coef32 * static_cast<float>(t);
     } else {
         return factor(r, xs, m);
@@ -176,9 +194,19 @@ struct SweepPath<T, FK_LOOKUP> {
     template <int K>
     using Samples = LaneTable<K>;
 };
-// ... and of the final node, whose factors are binary64 at every precision.
+template <>
+struct SweepPath<float, FK_LOOKUP_T32> {
+    using Rec = EdgeRecL;
+    template <int K>
+    using Samples = LaneTable32<K>;
+};
+// ... and of the final node, whose factors are binary64 at every precision
+// (from the binary64 tables also when the levels read binary32 copies).
 template <int KIND>
-using FinalPath = SweepPath<double, KIND>;
+using FinalPath = SweepPath<double, KIND == FK_LOOKUP_T32 ? FK_LOOKUP : KIND>;
+// Element type of the per-sample input the interior levels read.
+template <int KIND>
+using SampleElem = std::conditional_t<KIND == FK_LOOKUP_T32, float, double>;
 
 // One wave computes destination rows [jbeg, jend) of a level for the tile at
 // tbase (64*K samples).  The rows' edges form one contiguous stream, walked in
@@ -444,6 +472,8 @@ struct FusedGraph {
     int64_t S;
     double *out;
     int32_t *out_exp;
+    const float *t32 = nullptr;  // FK_LOOKUP_T32: binary32 tables [n_slots][ld32] for the interior levels
+    int64_t ld32 = 0;
 };
 
 // One level of the whole-graph sweep for a wave's rows [jb, jb + nb): the
@@ -519,9 +549,12 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
                                            int wave, int lane) {
     constexpr int kTile = kWave * K;
     typename SweepPath<T, KIND>::template Samples<K> xs;
-    xs.load(G.x, G.S, G.S, tbase, lane);
+    if constexpr (KIND == FK_LOOKUP_T32)
+        xs.load(G.t32, G.S, G.ld32, tbase, lane);
+    else
+        xs.load(G.x, G.S, G.S, tbase, lane);
     const typename SweepPath<T, KIND>::Rec *edges;
-    if constexpr (KIND == FK_LOOKUP)
+    if constexpr (KIND != FK_RATIONAL)
         edges = G.edgesL;
     else if constexpr (sizeof(T) == sizeof(double))
         edges = G.edges;
@@ -583,7 +616,7 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
     else if (wave < nq)
         xd.load(G.x, G.S, G.S, tbase, lane);
     const typename FinalPath<KIND>::Rec *fedges;
-    if constexpr (KIND == FK_LOOKUP)
+    if constexpr (KIND != FK_RATIONAL)
         fedges = G.edgesL + lf.e_begin;
     else
         fedges = G.edges + lf.e_begin;
