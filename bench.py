@@ -63,9 +63,15 @@ def record_bytes(g, precision: str) -> int:
     return 4 + 6 * 8 if precision == "fp64" else 4 + 5 * 4
 
 
-def input_bytes(g, S_pad: int) -> int:
-    """Per-sample inputs read once: 3 coordinates, or the table (n_slots entries), in binary64."""
-    return 8 * g.n_inputs * S_pad
+def table_entry_bytes(g, precision: str) -> int:
+    """Bytes of a per-sample input as the interior levels read it: binary64 coordinates or table entries,
+    except the binary32 paths of a lookup graph, which read a binary32 copy of the tables."""
+    return 8 if g.kind != "lookup" or precision == "fp64" else 4
+
+
+def input_bytes(g, S_pad: int, precision: str) -> int:
+    """Per-sample inputs read once: 3 coordinates, or the table (n_slots entries)."""
+    return table_entry_bytes(g, precision) * g.n_inputs * S_pad
 
 
 def level_bytes(g, S_pad: int, precision: str) -> list:
@@ -78,7 +84,7 @@ def level_bytes(g, S_pad: int, precision: str) -> list:
     for l in range(1, g.L):
         w_prev = 0 if l == 1 else int(g.widths[l - 1])  # level 1 reads the root's constant 1
         out.append((w_prev + int(g.widths[l])) * S_pad * B + int(g.epl[l - 1]) * rec
-                   + 4 * (int(g.widths[l]) + 1) + input_bytes(g, S_pad))
+                   + 4 * (int(g.widths[l]) + 1) + input_bytes(g, S_pad, precision))
     return out
 
 
@@ -201,7 +207,7 @@ def roofline(g, S_pad, precision, kern, steps, workload):
         fl = flops_per_edge_sample(g)
         alu = es_step / n_launch * fl / t_launch / 1e12
         # compulsory HBM bytes: per-sample inputs in, out written, edge records once per 64-sample workgroup
-        hbm_bytes = input_bytes(g, S_pad) + 8 * S_pad + g.n_edges * record_bytes(g, precision) * (S_pad // 64)
+        hbm_bytes = input_bytes(g, S_pad, precision) + 8 * S_pad + g.n_edges * record_bytes(g, precision) * (S_pad // 64)
         r = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
              "frac": alu / VALU_PEAK_TFLOPS[precision], "kernel": "fused_sweep_kernel",
              "avg_launch_us": kern[dom]["avg_us"], "launches_per_step": n_launch,
@@ -209,7 +215,7 @@ def roofline(g, S_pad, precision, kern, steps, workload):
              "other_term": {"hbm_gbs_compulsory": hbm_bytes / t_launch / 1e9}}
         if g.kind == "lookup":
             # the binding stream is the table entry each edge-sample reads (from L1/L2)
-            r["other_term"]["table_gbs_read"] = es_step / n_launch * 8 / t_launch / 1e9
+            r["other_term"]["table_gbs_read"] = es_step / n_launch * table_entry_bytes(g, precision) / t_launch / 1e9
     else:
         r = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "kernel": dom}
     r["traffic"] = profiled_traffic(r.get("kernel"), workload, precision)

@@ -197,7 +197,8 @@ cos_status cos_graph_export_lookup(const cos_graph *g, int32_t *src, int32_t *ds
 
 /*
  * Device scratch bytes cos_evaluate needs for S samples at precision p
- * (level buffers, exponent rows and final-node partial sums).
+ * (level buffers, exponent rows and final-node partial sums; for the binary32
+ * precisions of a lookup graph also a binary32 copy of the sample tables).
  * Errors: COS_EINVAL.
  */
 cos_status cos_evaluate_workspace_size(const cos_graph *g, int64_t S, cos_precision p,
