@@ -420,9 +420,9 @@ def _pct(v, q):
 def serving_leg(P, args):
     """Continuous-batching server vs one-at-a-time cos_evaluate on the serving request stream.
 
-    Runs: a t=0 burst of every request (batched FP64, batched FP32-rescaled), then Poisson arrivals at
-    load x the measured batched-FP64 capacity, each trace replayed by batched FP64, batched FP32-rescaled
-    and single-request FP64 (cos_evaluate, one request at a time, in arrival order).  Latency of a request =
+    Runs: a t=0 burst of every request (batched FP64, FP32-rescaled, and the two 16-bit storage formats),
+    then Poisson arrivals at load x the measured batched-FP64 capacity, each trace replayed by batched
+    FP64, batched FP32-rescaled and single-request FP64 (cos_evaluate, one request at a time, in arrival order).  Latency of a request =
     completion - arrival; throughput = total edge-samples / (last completion - first arrival).
     """
     import torch
@@ -440,7 +440,8 @@ def serving_leg(P, args):
     Ss = np.array([r["S"] for r in reqs])
     off = np.concatenate([[0], np.cumsum(Ss)])
     xs = [torch.from_numpy(r["x"]).to(dev) for r in reqs]
-    outs = {k: torch.empty(int(off[-1]), dtype=torch.float64, device=dev) for k in ("fp64", "fp32r", "single")}
+    outs = {k: torch.empty(int(off[-1]), dtype=torch.float64, device=dev)
+            for k in ("fp64", "fp32r", "fp16r", "bf16r", "single")}
 
     def out_view(kind, i):
         return outs[kind][int(off[i]):int(off[i + 1])]
@@ -505,12 +506,12 @@ def serving_leg(P, args):
                 "p99_ms": _pct(lat, 99)}
 
     zeros = np.zeros(len(reqs))
-    for p in ("fp64", "fp32r"):  # warm-up: code objects, first-touch of the arena
+    for p in ("fp64", "fp32r", "fp16r", "bf16r"):  # warm-up: code objects, first-touch of the arena
         batched(p, zeros, n=256)
     single(zeros, n=64)
     res = {"workload": SERVING_TEXT, "requests": len(reqs), "graphs": len(graphs), "total_edge_samples": total_es,
            "server": {"hbm_budget_bytes": budget, "max_slots": args.serve_slots}}
-    res["burst"] = {p: batched(p, zeros) for p in ("fp64", "fp32r")}
+    res["burst"] = {p: batched(p, zeros) for p in ("fp64", "fp32r", "fp16r", "bf16r")}
     res["burst"]["fp64_single"] = single(zeros)
     cap_rps = len(reqs) / (res["burst"]["fp64"]["makespan_ms"] / 1e3)
     rng = np.random.default_rng(4)

@@ -359,11 +359,13 @@ cos_status cos_server_add_graph(cos_server *srv, const cos_graph *g, int32_t *gi
 
 /*
  * Queue a request: x_dev device float64[3][S], out_dev device float64[S],
- * out_exp_dev device int32[S] or NULL (as for cos_evaluate).  The caller keeps
- * them alive until the request ends (poll/wait return a final status).  Never
- * blocks.  Errors: COS_EINVAL (unknown gid, S < 1, bad or 16-bit precision, S too large
- * for one sweep), COS_ENOMEM (the request's workspace exceeds the whole
- * budget, so it could never be admitted).
+ * out_exp_dev device int32[S] or NULL (as for cos_evaluate).  Every precision
+ * is served; 16-bit storage runs on the streamed plan, as in cos_evaluate.
+ * The caller keeps them alive until the request ends (poll/wait return a
+ * final status).  Never blocks.  Errors: COS_EINVAL (unknown gid, S < 1, bad
+ * precision or one cos_evaluate would refuse for this graph, S too large for
+ * one sweep), COS_ENOMEM (the request's workspace exceeds the whole budget, so
+ * it could never be admitted).
  */
 cos_status cos_server_submit(cos_server *srv, int32_t gid, const double *x_dev, int64_t S, cos_precision p,
                              double *out_dev, int32_t *out_exp_dev, uint64_t *ticket);

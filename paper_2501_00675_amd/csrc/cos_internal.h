@@ -108,6 +108,7 @@ struct Graph {
     EdgeRec32 *d_edges32 = nullptr;   // binary32 records (interior levels of the binary32 sweeps)
     EdgeRecL *d_edgesL = nullptr;     // lookup records (every level, every precision)
     LevelDev *d_levels = nullptr;     // L entries
+    int32_t *d_h16 = nullptr;         // h16 on the device (L entries; NULL when h16 is empty)
     int device = 0;
     cos_path path = COS_PATH_AUTO;    // kernel plan chosen by cos_graph_set_path
 };
@@ -146,7 +147,7 @@ constexpr int kFusedWaves = 16;      // wavefronts per workgroup of the LDS-resi
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Precisions whose interior levels carry the per-(level, sample) exponent.
-inline bool is_rescaled(cos_precision p) {
+__host__ __device__ inline bool is_rescaled(cos_precision p) {
     return p == COS_FP32_RESCALED || p == COS_FP16_RESCALED || p == COS_BF16_RESCALED;
 }
 // Bytes of one stored level value.

@@ -403,7 +403,8 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     const size_t off_rec32 = off_rec + round_up(recs.size() * sizeof(EdgeRec), 256);
     const size_t off_recL = off_rec32 + round_up(recs32.size() * sizeof(EdgeRec32), 256);
     const size_t off_lev = off_recL + round_up(recsL.size() * sizeof(EdgeRecL), 256);
-    const size_t total = off_lev + round_up(L * sizeof(LevelDev), 256);
+    const size_t off_h16 = off_lev + round_up(L * sizeof(LevelDev), 256);
+    const size_t total = off_h16 + round_up(G.h16.size() * sizeof(int32_t), 256);
     hipError_t err = hipGetDevice(&G.device);
     if (err != hipSuccess)
         return hip_fail(err, "hipGetDevice");
@@ -417,6 +418,7 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     G.d_edges32 = lookup ? nullptr : reinterpret_cast<EdgeRec32 *>(base + off_rec32);
     G.d_edgesL = lookup ? reinterpret_cast<EdgeRecL *>(base + off_recL) : nullptr;
     G.d_levels = reinterpret_cast<LevelDev *>(base + off_lev);
+    G.d_h16 = G.h16.empty() ? nullptr : reinterpret_cast<int32_t *>(base + off_h16);
     err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
     if (err == hipSuccess && !recs.empty())
         err = hipMemcpy(G.d_edges, recs.data(), recs.size() * sizeof(EdgeRec), hipMemcpyHostToDevice);
@@ -426,6 +428,8 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
         err = hipMemcpy(G.d_edgesL, recsL.data(), recsL.size() * sizeof(EdgeRecL), hipMemcpyHostToDevice);
     if (err == hipSuccess)
         err = hipMemcpy(G.d_levels, ldev.data(), L * sizeof(LevelDev), hipMemcpyHostToDevice);
+    if (err == hipSuccess && G.d_h16)
+        err = hipMemcpy(G.d_h16, G.h16.data(), G.h16.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (err != hipSuccess) {
         (void)hipFree(G.d_base);
         return hip_fail(err, "hipMemcpy(graph)");

@@ -76,8 +76,11 @@ __device__ __forceinline__ void serve_fused_rows(const ServeReqDev &r, uint32_t 
 }
 
 // Interior level l for a row group of 32 rows (8 per wave) and a tile of 256
-// samples; the level buffers alternate as in the standalone sweep.
-template <typename T, bool RESCALE, int KIND>
+// samples; the level buffers (values of type V) alternate as in the standalone
+// sweep, and so do the exponent rows: level l is scaled by row l-1 (row 0 holds
+// level 1's headroom, 0 unless binary16) and folds its largest |value|, times
+// 2^h_{l+1} for binary16, into row l.
+template <typename T, bool RESCALE, int KIND, typename V>
 __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_t local, uint32_t n_rg,
                                             uint32_t *red, int wave, int lane) {
     constexpr int K = kServeLevelK;
@@ -85,10 +88,10 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     const uint32_t tile = local / n_rg;
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
     const LevelDev lv = load_level(r.levels, l - 1);
-    T *const b0 = reinterpret_cast<T *>(r.ws + r.off_buf0);
-    T *const b1 = reinterpret_cast<T *>(r.ws + r.off_buf1);
-    T *cur = (l - 1) & 1 ? b1 : b0;
-    const T *prev = (l - 2) & 1 ? b1 : b0;
+    V *const b0 = reinterpret_cast<V *>(r.ws + r.off_buf0);
+    V *const b1 = reinterpret_cast<V *>(r.ws + r.off_buf1);
+    V *cur = (l - 1) & 1 ? b1 : b0;
+    const V *prev = (l - 2) & 1 ? b1 : b0;
     uint32_t *maxbits = reinterpret_cast<uint32_t *>(r.ws + r.off_maxbits);
     typename SweepPath<T, KIND>::template Samples<K> smp;
     smp.load(r.x, r.S, r.S, tbase, lane);
@@ -103,22 +106,29 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     uint32_t lmax[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
-        esh[m] = (RESCALE && l >= 2) ? ilogb_bits(maxbits[static_cast<int64_t>(l - 1) * r.S_pad + tbase + lane + kWave * m])
-                                     : 0;
+        esh[m] = RESCALE ? ilogb_bits(maxbits[static_cast<int64_t>(l - 1) * r.S_pad + tbase + lane + kWave * m]) : 0;
         lmax[m] = 0u;
     }
     const int jbeg = min(static_cast<int>(rg) * kServeLevelRowsPerItem + wave * kServeLevelRows, lv.w_dst);
     const int jend = min(jbeg + kServeLevelRows, lv.w_dst);
     const int32_t *rp = r.row_ptr + lv.rp_begin;
     if (l == 1)
-        level_wave_rows<T, K, true, RESCALE, KIND, T>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp,
+        level_wave_rows<T, K, true, RESCALE, KIND, V>(rp, recs, jbeg, jend, nullptr, cur, r.S_pad, tbase, lane, smp,
                                                       esh, lmax);
     else
-        level_wave_rows<T, K, false, RESCALE, KIND, T>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp,
+        level_wave_rows<T, K, false, RESCALE, KIND, V>(rp, recs, jbeg, jend, prev, cur, r.S_pad, tbase, lane, smp,
                                                        esh, lmax);
     if constexpr (RESCALE) {
-        if (l <= r.L - 2)
+        if (l <= r.L - 2) {
+            if constexpr (std::is_same_v<V, _Float16>) {
+                const int32_t h_next = r.h16[l + 1];
+                if (h_next)  // exact: |value| <= 2^15 and h_next <= 96
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        lmax[m] = abs_bits(ldexpf(__uint_as_float(lmax[m]), h_next));
+            }
             fold_max<K, 4>(red, lmax, wave, lane, maxbits + static_cast<int64_t>(l) * r.S_pad + tbase);
+        }
     }
 }
 
@@ -204,22 +214,31 @@ __global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *_
             const int l = static_cast<int>(en.level);
             uint32_t *red = reinterpret_cast<uint32_t *>(lds);
             if (r.precision == COS_FP64)
-                serve_level<double, false, KIND>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<double, false, KIND, double>(r, l, local, en.n_rg, red, wave, lane);
             else if (r.precision == COS_FP32_RESCALED)
-                serve_level<float, true, KIND>(r, l, local, en.n_rg, red, wave, lane);
-            else
-                serve_level<float, false, KIND>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<float, true, KIND, float>(r, l, local, en.n_rg, red, wave, lane);
+            else if (r.precision == COS_BF16_RESCALED)
+                serve_level<float, true, KIND, __bf16>(r, l, local, en.n_rg, red, wave, lane);
+            else if (r.precision == COS_FP16_RESCALED) {
+                if constexpr (KIND == FK_RATIONAL)  // binary16 needs the factors' bound: rational only
+                    serve_level<float, true, KIND, _Float16>(r, l, local, en.n_rg, red, wave, lane);
+            } else
+                serve_level<float, false, KIND, float>(r, l, local, en.n_rg, red, wave, lane);
         } else if (kind == SK_FINAL) {
             double *red = reinterpret_cast<double *>(lds);
             if (r.precision == COS_FP64)
                 serve_final<double, KIND>(r, local, red, wave, lane);
+            else if (r.precision == COS_BF16_RESCALED)
+                serve_final<__bf16, KIND>(r, local, red, wave, lane);
+            else if (r.precision == COS_FP16_RESCALED)
+                serve_final<_Float16, KIND>(r, local, red, wave, lane);
             else
                 serve_final<float, KIND>(r, local, red, wave, lane);
         } else {  // SK_COMBINE
             const int64_t s = static_cast<int64_t>(local) * kServeCombineTile + threadIdx.x;
             if (s < r.S)
                 final_combine_one(reinterpret_cast<const double *>(r.ws + r.off_partial), r.final_chunks, r.S_pad, s,
-                                  r.precision == COS_FP32_RESCALED
+                                  is_rescaled(static_cast<cos_precision>(r.precision))
                                       ? reinterpret_cast<const uint32_t *>(r.ws + r.off_maxbits)
                                       : nullptr,
                                   r.L, r.out, r.out_exp);

@@ -28,6 +28,7 @@ struct ServeReqDev {
     const EdgeRec32 *edges32;
     const EdgeRecL *edgesL;   // lookup factors (x is then the sample's table, [n_slots][S])
     const LevelDev *levels;
+    const int32_t *h16;       // binary16 storage: the graph's headroom exponents per node level
     const double *x;
     double *out;
     int32_t *out_exp;

@@ -177,6 +177,7 @@ hipError_t Server::setup(Request *r) {
     d.edges32 = g.d_edges32;
     d.edgesL = g.d_edgesL;
     d.levels = g.d_levels;
+    d.h16 = g.d_h16;
     d.x = r->x;
     d.out = r->out;
     d.out_exp = r->out_exp;
@@ -194,9 +195,15 @@ hipError_t Server::setup(Request *r) {
     d.off_red = static_cast<uint32_t>(r->flay.off_red);
     d.off_part = static_cast<uint32_t>(r->flay.off_part);
     hipError_t err = hipMemcpyAsync(d_reqs + r->slot, &d, sizeof(ServeReqDev), hipMemcpyHostToDevice, stream);
-    if (err == hipSuccess && !r->fused && r->p == COS_FP32_RESCALED)
-        err = launch_fill_u32(reinterpret_cast<uint32_t *>(d.ws + d.off_maxbits), 0u,
-                              static_cast<int64_t>(g.L + 1) * r->wlay.S_pad, stream);
+    // exponent rows: row 0 holds level 1's headroom 2^h_1 (binary16; else 0 = no
+    // shift), rows 1..L start at zero for the levels' maxima
+    if (err == hipSuccess && !r->fused && is_rescaled(r->p)) {
+        uint32_t *rows = reinterpret_cast<uint32_t *>(d.ws + d.off_maxbits);
+        const int32_t h1 = r->p == COS_FP16_RESCALED && g.L >= 2 ? g.h16[1] : 0;
+        err = launch_fill_u32(rows, h1 ? static_cast<uint32_t>(127 + h1) << 23 : 0u, r->wlay.S_pad, stream);
+        if (err == hipSuccess)
+            err = launch_fill_u32(rows + r->wlay.S_pad, 0u, static_cast<int64_t>(g.L) * r->wlay.S_pad, stream);
+    }
     return err;
 }
 
@@ -421,9 +428,8 @@ extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double
                                         double *out_dev, int32_t *out_exp_dev, uint64_t *ticket) {
     if (!h || !x_dev || !out_dev || !ticket)
         return fail(COS_EINVAL, "cos_server_submit: NULL argument");
-    if (p == COS_FP16_RESCALED || p == COS_BF16_RESCALED)
-        return fail(COS_EINVAL, "cos_server_submit: 16-bit level storage is not served (cos_evaluate only)");
-    if (p != COS_FP64 && p != COS_FP32_RESCALED && p != COS_FP32)
+    if (p != COS_FP64 && p != COS_FP32_RESCALED && p != COS_FP32 && p != COS_FP16_RESCALED &&
+        p != COS_BF16_RESCALED)
         return fail(COS_EINVAL, "cos_server_submit: unknown precision");
     if (S < 1 || S > INT32_MAX)
         return fail(COS_EINVAL, "cos_server_submit: S must be in 1..2^31-1");
@@ -436,6 +442,12 @@ extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double
         r->g = s->graphs[gid];
     }
     const Graph &g = *r->g;
+    // the conditions cos_evaluate refuses for 16-bit storage
+    if (value_bytes(p) == 2 && g.path == COS_PATH_FUSED)
+        return fail(COS_EINVAL, "cos_server_submit: 16-bit level storage runs on the streamed plan only");
+    if (p == COS_FP16_RESCALED && g.h16.empty())
+        return fail(COS_EINVAL, "cos_server_submit: binary16 storage needs rational factors with level row sums of "
+                                "|a| below 2^110 (use COS_BF16_RESCALED or COS_FP32_RESCALED)");
     r->x = x_dev;
     r->out = out_dev;
     r->out_exp = out_exp_dev;

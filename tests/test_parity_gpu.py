@@ -342,13 +342,16 @@ def test_timing_probe_counts_launches(P):
     assert n_f == 1 and ms_f > 0
 
 
-@pytest.mark.parametrize("name,precision", [("mid", "fp64"), ("mid", "fp32r"), ("precision", "fp16r"),
-                                            ("precision", "fp32r")])
-def test_evaluate_captured_in_a_graph_replays_bit_identical(P, name, precision):
+@pytest.mark.parametrize("name,precision,factor", [("mid", "fp64", "rational"), ("mid", "fp32r", "rational"),
+                                                   ("precision", "fp16r", "rational"),
+                                                   ("precision", "fp32r", "rational"),
+                                                   ("mid", "fp32r", "lookup"), ("precision", "bf16r", "lookup")])
+def test_evaluate_captured_in_a_graph_replays_bit_identical(P, name, precision, factor):
     # cos_evaluate with a caller workspace issues kernels only (no allocation, no memset), so it
     # can be captured in a HIP graph; every replay, with new samples written in between, must
-    # give the eager result's bits
-    g, x = make_config(name, S=2048)
+    # give the eager result's bits (the lookup cases include the binary32 table copy, on the
+    # fused and on the streamed plan)
+    g, x = make_config(name, S=2048, factor=factor)
     G = graph(P, g)
     rng = np.random.default_rng(5)
     xs = [x] + [x + rng.normal(0, 0.05, x.shape) for _ in range(3)]

@@ -147,6 +147,46 @@ def test_lookup_graphs_served_bit_identical_alone_and_mixed(P):
         assert_parity(tickets[i].out.cpu().numpy()[idx], V, Q, p, f"lookup mix {i}")
 
 
+def test_16bit_storage_served_bit_identical_alone_and_mixed(P):
+    # binary16 and bfloat16 level storage in the serving runtime: 16-bit requests run on the
+    # streamed plan (also for a graph that takes the whole-graph plan at 32 and 64 bits) and
+    # share steps with FP64 and FP32-rescaled requests; every result must equal cos_evaluate's
+    # bits at the same precision (whose error is checked against the oracle's bound elsewhere)
+    graphs = [make_config("mid", S=1500, width=200, L=6, degree=3, seed=41),
+              make_config("mid", S=1300, width=900, L=7, degree=3, seed=42),
+              make_config("mid", S=1100, factor="lookup", width=600, L=5, degree=3, seed=43)]
+    Gs = [P.Graph.from_leveled(g) for g, _ in graphs]
+    assert Gs[0].info()["fused_mask"] & 1 and not Gs[1].info()["fused_mask"]
+    jobs = [(0, "fp16r"), (0, "bf16r"), (1, "fp16r"), (1, "bf16r"), (2, "bf16r"), (0, "fp64"), (1, "fp32r"),
+            (2, "fp32r"), (1, "fp16r")]
+    xs = [to_dev(graphs[gi][1]) for gi, _ in jobs]
+    refs = [gpu_eval(Gs[gi], graphs[gi][1], p) for gi, p in jobs]
+    torch.cuda.synchronize()
+    say(f"serve 16-bit mix: {len(jobs)} requests")
+    with P.Server(512 * MiB, 16) as srv:
+        gids = [srv.add_graph(G) for G in Gs]
+        tickets = [srv.submit(gids[gi], x, p, sync_inputs=False) for (gi, p), x in zip(jobs, xs)]
+        stats = [srv.wait(t) for t in tickets]
+        s = srv.stats()
+    assert all(st["status"] == 0 for st in stats) and s["max_step_requests"] > 1
+    for i, (t, r) in enumerate(zip(tickets, refs)):
+        assert np.array_equal(bits(t.out.cpu().numpy()), bits(r)), f"request {i} {jobs[i]}"
+    with P.Server(256 * MiB, 2) as srv:
+        gid = srv.add_graph(Gs[1])
+        t = srv.submit(gid, xs[2], "fp16r")
+        srv.wait(t)
+        assert np.array_equal(bits(t.out.cpu().numpy()), bits(refs[2]))
+        # refused as by cos_evaluate: binary16 with lookup factors, 16-bit with the whole-graph plan forced
+        gl = srv.add_graph(Gs[2])
+        with pytest.raises(P.CosError, match="binary16"):
+            srv.submit(gl, xs[4], "fp16r")
+        g0 = srv.add_graph(Gs[0])
+        Gs[0].set_path("fused")
+        with pytest.raises(P.CosError, match="streamed plan"):
+            srv.submit(g0, xs[0], "bf16r")
+        Gs[0].set_path("auto")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32r"])
 def test_admission_waits_for_budget(P, precision):
     g, x = make_config("mid", S=2000, width=700, L=5, degree=3)
