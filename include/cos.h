@@ -304,7 +304,9 @@ cos_status cos_mc_run(const cos_graph *g, cos_precision p, int64_t C, double *x_
  * one stage per step, where a step is one level-synchronous launch shared by
  * all admitted requests (replayed from an instantiated HIP graph): a graph whose
  * widest level fits in LDS completes in one step, a wider graph advances one
- * level per step, then its final node in two more.  Requests that arrive while
+ * level per step, then its final node in two more (a lookup request at a
+ * binary32 precision first takes one step to copy its tables to binary32,
+ * as cos_evaluate does).  Requests that arrive while
  * others run join the next step (continuous batching).  Each result is
  * bit-identical to cos_evaluate on the same graph, samples and precision.
  */

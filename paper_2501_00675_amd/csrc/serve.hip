@@ -94,9 +94,12 @@ __device__ __forceinline__ void serve_level(const ServeReqDev &r, int l, uint32_
     const V *prev = (l - 2) & 1 ? b1 : b0;
     uint32_t *maxbits = reinterpret_cast<uint32_t *>(r.ws + r.off_maxbits);
     typename SweepPath<T, KIND>::template Samples<K> smp;
-    smp.load(r.x, r.S, r.S, tbase, lane);
+    if constexpr (KIND == FK_LOOKUP_T32)
+        smp.load(r.t32, r.S, r.S_pad, tbase, lane);
+    else
+        smp.load(r.x, r.S, r.S, tbase, lane);
     const typename SweepPath<T, KIND>::Rec *recs;
-    if constexpr (KIND == FK_LOOKUP)
+    if constexpr (KIND != FK_RATIONAL)
         recs = r.edgesL;
     else if constexpr (sizeof(T) == sizeof(double))
         recs = r.edges;
@@ -194,7 +197,8 @@ __global__ __launch_bounds__(kFusedThreads) void serve_fused_kernel(const StepTa
 }
 
 // Level, final-node and combine items of section SEC (SS_STREAMED, or
-// SS_STREAMED_LOOKUP with KIND lookup).
+// SS_STREAMED_LOOKUP with KIND lookup, where the binary32 precisions read the
+// binary32 copy of the tables made by the request's first stage).
 template <int KIND, uint32_t SEC>
 __global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *__restrict__ tab,
                                                               const ServeReqDev *__restrict__ reqs) {
@@ -211,19 +215,28 @@ __global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *_
         const uint32_t local = item - en.item_base;
         const uint32_t kind = en.kind;
         if (kind == SK_LEVEL) {
+            constexpr int K32 = KIND == FK_LOOKUP ? FK_LOOKUP_T32 : KIND;  // kind of the binary32 levels
             const int l = static_cast<int>(en.level);
             uint32_t *red = reinterpret_cast<uint32_t *>(lds);
             if (r.precision == COS_FP64)
                 serve_level<double, false, KIND, double>(r, l, local, en.n_rg, red, wave, lane);
             else if (r.precision == COS_FP32_RESCALED)
-                serve_level<float, true, KIND, float>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<float, true, K32, float>(r, l, local, en.n_rg, red, wave, lane);
             else if (r.precision == COS_BF16_RESCALED)
-                serve_level<float, true, KIND, __bf16>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<float, true, K32, __bf16>(r, l, local, en.n_rg, red, wave, lane);
             else if (r.precision == COS_FP16_RESCALED) {
                 if constexpr (KIND == FK_RATIONAL)  // binary16 needs the factors' bound: rational only
                     serve_level<float, true, KIND, _Float16>(r, l, local, en.n_rg, red, wave, lane);
             } else
-                serve_level<float, false, KIND, float>(r, l, local, en.n_rg, red, wave, lane);
+                serve_level<float, false, K32, float>(r, l, local, en.n_rg, red, wave, lane);
+        } else if (kind == SK_TABLE32) {
+            // entries [local * 256, local * 256 + 256) of [n_slots][S_pad] (S_pad a multiple of 256)
+            if constexpr (KIND == FK_LOOKUP) {
+                const int64_t i = static_cast<int64_t>(local) * kServeCombineTile + threadIdx.x;
+                const int64_t row = i / r.S_pad, s = i - row * r.S_pad;
+                if (row < r.n_slots)
+                    r.t32[i] = s < r.S ? static_cast<float>(r.x[row * r.S + s]) : 0.0f;
+            }
         } else if (kind == SK_FINAL) {
             double *red = reinterpret_cast<double *>(lds);
             if (r.precision == COS_FP64)

@@ -12,6 +12,7 @@ enum ServeKind : uint32_t {
     SK_LEVEL = 1,    // one interior level: items = (row group of 32 rows) x (tile of 256 samples)
     SK_FINAL = 2,    // final-node partial sums: items = (chunk of 256 edges) x (tile of 128 samples)
     SK_COMBINE = 3,  // final-node combine: items = tiles of 256 samples
+    SK_TABLE32 = 4,  // binary32 copy of a lookup request's tables: items = 256 entries
 };
 
 constexpr int kServeLevelK = 4;                            // samples per lane, level items
@@ -33,6 +34,7 @@ struct ServeReqDev {
     double *out;
     int32_t *out_exp;
     char *ws;                 // workspace of a streamed request (level buffers, exponents, partials)
+    float *t32;               // streamed lookup request at binary32: its tables' binary32 copy [n_slots][S_pad]
     int64_t S;
     int64_t S_pad;
     uint64_t off_buf0, off_buf1, off_maxbits, off_partial;
@@ -40,6 +42,7 @@ struct ServeReqDev {
     int32_t precision;        // cos_precision
     int32_t rows_variant;     // fused requests: rows per wave (compile-time variant)
     int32_t final_chunks;     // streamed requests: final-node partial rows
+    int32_t n_slots;          // lookup factors: table entries per sample
     uint32_t off_red, off_part;  // fused requests: LDS layout (one sample per lane)
 };
 

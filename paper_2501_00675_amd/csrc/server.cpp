@@ -41,6 +41,7 @@ struct Request {
     int64_t S = 0;
     cos_precision p = COS_FP64;
     bool fused = false;
+    bool table32 = false;    // streamed lookup request at binary32: its first stage copies the tables
     int section = SS_FUSED;  // ServeSection of its work
     FusedLayout flay;
     Workspace wlay;
@@ -147,6 +148,15 @@ uint32_t stage_items(const Request &r, int stage, uint32_t *n_rg, uint32_t *kind
         *n_rg = 1;
         return static_cast<uint32_t>((r.S + kWave - 1) / kWave);
     }
+    if (r.table32) {
+        if (stage == 0) {
+            *kind = SK_TABLE32;
+            *level = 0;
+            *n_rg = 1;
+            return static_cast<uint32_t>(static_cast<int64_t>(g.n_slots) * r.wlay.S_pad / kServeCombineTile);
+        }
+        --stage;
+    }
     const int L = g.L;
     if (stage < L - 1) {  // interior level stage + 1
         const int l = stage + 1;
@@ -192,6 +202,8 @@ hipError_t Server::setup(Request *r) {
     d.precision = r->p;
     d.rows_variant = rows_variant((g.max_width + kFusedWaves - 1) / kFusedWaves);
     d.final_chunks = r->wlay.final_chunks;
+    d.n_slots = g.n_slots;
+    d.t32 = r->table32 ? reinterpret_cast<float *>(d.ws + r->wlay.off_table32) : nullptr;
     d.off_red = static_cast<uint32_t>(r->flay.off_red);
     d.off_part = static_cast<uint32_t>(r->flay.off_part);
     hipError_t err = hipMemcpyAsync(d_reqs + r->slot, &d, sizeof(ServeReqDev), hipMemcpyHostToDevice, stream);
@@ -464,9 +476,10 @@ extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double
     } else {
         if (max_chunk(g, p) < S)
             return fail(COS_EINVAL, "cos_server_submit: S too large for one sweep; use cos_evaluate");
-        r->wlay = layout_for_chunk(g, S, p, false);
+        r->table32 = uses_table32(g, p);
+        r->wlay = layout_for_chunk(g, S, p, r->table32);
         r->footprint = r->wlay.bytes;
-        r->n_stages = g.L + 1;
+        r->n_stages = g.L + 1 + (r->table32 ? 1 : 0);
         if (r->footprint > s->budget)
             return fail(COS_ENOMEM, "cos_server_submit: the request's workspace (" + std::to_string(r->footprint) +
                                         " bytes) exceeds the server's HBM budget");
