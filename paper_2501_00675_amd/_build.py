@@ -67,9 +67,26 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    example = build_example()
     if verbose:
-        print(f"built {LIB} (build id {bid})")
+        print(f"built {LIB} (build id {bid}) and {example}")
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(PKG, "examples", "evaluate_layered.c")
+EXAMPLE = os.path.join(PKG, "examples", "evaluate_layered")
+
+
+def build_example() -> str:
+    """The C program that uses the library without Python (plain C, the system compiler)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__", f"-I{INCLUDE}",
+           f"-I{rocm}/include", EXAMPLE_SRC, f"-L{PKG}", "-lcosdag", f"-L{rocm}/lib", "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN/..", f"-Wl,-rpath,{rocm}/lib", "-o", EXAMPLE]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{r.stderr}")
+    return EXAMPLE
 
 
 if __name__ == "__main__":
