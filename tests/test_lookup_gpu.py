@@ -198,3 +198,27 @@ def test_lookup_graph_file_round_trip_bit_identical(P, tmp_path):
     assert G2.info()["kind"] == "lookup" and G2.n_inputs == g.n_slots
     for precision in ("fp64", "fp32r"):
         assert np.array_equal(gpu_eval(G, T, precision), gpu_eval(G2, T, precision))
+
+
+@pytest.mark.parametrize("path", ["fused", "streamed"])
+def test_binary32_table_copy_workspace(P, path):
+    # the binary32 paths of a lookup graph copy the tables into the workspace: its size covers
+    # them on both plans, a fused-plan workspace without room for them is refused, and a small
+    # streamed workspace sweeps in chunks with the same bits
+    g, T = make_config("mid", S=3000, factor="lookup")
+    G = graph(P, g).set_path(path)
+    S, n = T.shape[1], T.shape[0]
+    need32, need64 = G.workspace_bytes(S, "fp32r"), G.workspace_bytes(S, "fp64")
+    assert need32 >= n * S * 4
+    say(f"lookup table copy workspace {path}: {need32} bytes (FP64 {need64})")
+    xd = to_dev(T)
+    ref = gpu_eval(G, T, "fp32r")
+    if path == "fused":
+        small = torch.empty(256, dtype=torch.uint8, device="cuda:0")
+        with pytest.raises(P.CosError):
+            G.evaluate(xd, "fp32r", workspace=small)
+    else:
+        small = torch.empty(G.workspace_bytes(700, "fp32r"), dtype=torch.uint8, device="cuda:0")
+        y = G.evaluate(xd, "fp32r", workspace=small)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy().view(np.uint64), ref.view(np.uint64))

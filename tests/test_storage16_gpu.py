@@ -165,13 +165,20 @@ def test_16bit_is_streamed_only(P, precision):
 
 
 @pytest.mark.parametrize("precision", P16)
-def test_server_refuses_16bit(P, precision):
-    g, x = make_config("tiny", S=8)
+@pytest.mark.parametrize("S", [8, 300])
+def test_server_serves_16bit_on_the_streamed_plan(P, precision, S):
+    # the tiny graph takes the whole-graph plan at 32 and 64 bits; 16-bit requests run streamed
+    # (one step per level, then the final node's two) with cos_evaluate's bits
+    g, x = make_config("tiny", S=S)
+    G = P.Graph.from_leveled(g)
+    ref = gpu_eval(G, x, precision)
     srv = P.Server(hbm_budget=1 << 24, max_slots=4)
     try:
-        gid = srv.add_graph(P.Graph.from_leveled(g))
-        with pytest.raises(P.CosError, match="16-bit"):
-            srv.submit(gid, to_dev(x), precision)
+        gid = srv.add_graph(G)
+        t = srv.submit(gid, to_dev(x), precision)
+        st = srv.wait(t)
+        assert st["status"] == 0 and st["steps"] == g.L + 1
+        assert np.array_equal(t.out.cpu().numpy().view(np.uint64), ref.view(np.uint64))
     finally:
         srv.close()
 
