@@ -399,13 +399,14 @@ cos_status cos_server_get_stats(cos_server *srv, cos_server_stats *stats);
 cos_status cos_server_read_steps(cos_server *srv, cos_step_record *out, int64_t cap, int64_t *n);
 
 /*
- * Failure handling.  When the device set-up of a newly admitted request fails
- * (its slot entry upload or exponent-row clear), that request alone ends with
- * COS_EDEVICE and its slot and workspace are returned; the others go on.  A
- * failed step launch fails every active request of the server.  For tests of
- * that path without a device fault: make the set-up of the admission with
- * this index (0-based, in admission order; -1: none) fail as if the upload
- * had.  Errors: COS_EINVAL (NULL server, index < -1).
+ * Failure handling.  A newly admitted request's set-up (its slot entry and
+ * exponent rows, written on the device by the first step that includes it)
+ * is prepared on the host; a request whose set-up fails ends alone with
+ * COS_EDEVICE and its slot and workspace are returned, while the others go on.
+ * A failed step launch fails every active request of the server.  For tests
+ * of the per-request path without a device fault: make the set-up of the
+ * admission with this index (0-based, in admission order; -1: none) fail.
+ * Errors: COS_EINVAL (NULL server, index < -1).
  */
 cos_status cos_server_fail_admission(cos_server *srv, int64_t admission_index);
 

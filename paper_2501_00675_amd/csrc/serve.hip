@@ -260,9 +260,37 @@ __global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *_
     }
 }
 
+// The step's set-up: the slot entries of the newly admitted requests, then
+// their exponent rows (row 0 = row0, rows 1..L = 0), before the step kernels
+// (the next graph nodes) read them.
+__global__ __launch_bounds__(kBlock) void serve_setup_kernel(const StepTable *__restrict__ tab,
+                                                             ServeReqDev *__restrict__ reqs) {
+    static_assert(sizeof(ServeReqDev) % sizeof(uint32_t) == 0, "slot entries are copied word by word");
+    constexpr uint32_t kWords = sizeof(ServeReqDev) / sizeof(uint32_t);
+    const uint32_t n = tab->n_setup;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+    for (int64_t i = tid; i < static_cast<int64_t>(n) * kWords; i += stride) {
+        const StepSetup &su = tab->setup[i / kWords];
+        reinterpret_cast<uint32_t *>(reqs + su.slot)[i % kWords] =
+            reinterpret_cast<const uint32_t *>(&su.req)[i % kWords];
+    }
+    for (uint32_t e = 0; e < n; ++e) {
+        const StepSetup &su = tab->setup[e];
+        if (!su.fill)
+            continue;
+        uint32_t *rows = reinterpret_cast<uint32_t *>(su.req.ws + su.req.off_maxbits);
+        const int64_t total = static_cast<int64_t>(su.req.L + 1) * su.req.S_pad;
+        for (int64_t i = tid; i < total; i += stride)
+            rows[i] = i < su.req.S_pad ? su.row0 : 0u;
+    }
+}
+
 }  // namespace
 
 namespace {
+
+constexpr int kServeSetupGrid = 256;
 
 template <typename Kern>
 hipError_t allow_full_lds(Kern kern) {
@@ -272,7 +300,7 @@ hipError_t allow_full_lds(Kern kern) {
 
 }  // namespace
 
-hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, const ServeReqDev *d_reqs,
+hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, ServeReqDev *d_reqs,
                                   bool with_lookup, hipGraphExec_t *exec) {
     static std::atomic<bool> attr_set{false};
     if (!attr_set.load(std::memory_order_acquire)) {
@@ -293,6 +321,17 @@ hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, cons
     const StepTable *tab_arg = d_tab;
     const ServeReqDev *reqs_arg = d_reqs;
     void *args[] = {&tab_arg, &reqs_arg};
+    ServeReqDev *reqs_out = d_reqs;
+    void *setup_args[] = {&tab_arg, &reqs_out};
+    hipGraphNode_t setup = nullptr;
+    if (err == hipSuccess) {
+        hipKernelNodeParams kp{};
+        kp.func = reinterpret_cast<void *>(serve_setup_kernel);
+        kp.gridDim = dim3(kServeSetupGrid);
+        kp.blockDim = dim3(kBlock);
+        kp.kernelParams = setup_args;
+        err = hipGraphAddKernelNode(&setup, graph, &upload, 1, &kp);
+    }
     auto add = [&](void *func, bool fused) {
         if (err != hipSuccess)
             return;
@@ -303,7 +342,7 @@ hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, cons
         kp.sharedMemBytes = fused ? static_cast<unsigned>(kLdsBytes) : 0u;
         kp.kernelParams = args;
         hipGraphNode_t node = nullptr;
-        err = hipGraphAddKernelNode(&node, graph, &upload, 1, &kp);
+        err = hipGraphAddKernelNode(&node, graph, &setup, 1, &kp);
     };
     add(reinterpret_cast<void *>(serve_fused_kernel<FK_RATIONAL, SS_FUSED>), true);
     add(reinterpret_cast<void *>(serve_stream_kernel<FK_RATIONAL, SS_STREAMED>), false);

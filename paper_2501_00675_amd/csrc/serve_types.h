@@ -63,10 +63,24 @@ struct StepEntry {
 enum ServeSection : uint32_t { SS_FUSED = 0, SS_STREAMED = 1, SS_FUSED_LOOKUP = 2, SS_STREAMED_LOOKUP = 3,
                                SS_COUNT = 4 };
 
+// A newly admitted request's slot entry and the initial value of its exponent
+// rows, carried by the first step that includes the request: the step's set-up
+// kernel writes them before the step kernels run.
+struct StepSetup {
+    uint32_t slot;
+    uint32_t fill;  // 1: set the exponent rows (a streamed request at a rescaled precision)
+    uint32_t row0;  // exponent row 0: 2^h_1 as binary32 bits for binary16 storage, else 0 (rows 1..L: 0)
+    uint32_t pad;
+    ServeReqDev req;
+};
+
 struct StepTable {
     uint32_t n[SS_COUNT];      // entries per section
     uint32_t items[SS_COUNT];  // items per section
+    uint32_t n_setup;          // newly admitted requests whose set-up this step carries
+    uint32_t pad[3];
     StepEntry e[kServeMaxEntries];
+    StepSetup setup[kServeMaxEntries];
 };
 // First entry of section sec.
 __host__ __device__ inline uint32_t section_begin(const StepTable &t, uint32_t sec) {
@@ -77,10 +91,11 @@ __host__ __device__ inline uint32_t section_begin(const StepTable &t, uint32_t s
 }
 
 // Build the executable graph of one step: upload of the host table h_tab to
-// d_tab, then one kernel per section as independent branches reading d_tab
-// and the slot table d_reqs -- the two rational-factor sections only
-// (with_lookup false) or all four.
-hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, const ServeReqDev *d_reqs,
+// d_tab, the set-up kernel (slot entries and exponent rows of the newly
+// admitted requests), then one kernel per section as independent branches
+// reading d_tab and the slot table d_reqs -- the two rational-factor sections
+// only (with_lookup false) or all four.
+hipError_t serve_build_step_graph(StepTable *d_tab, const StepTable *h_tab, ServeReqDev *d_reqs,
                                   bool with_lookup, hipGraphExec_t *exec);
 
 }  // namespace cosdag

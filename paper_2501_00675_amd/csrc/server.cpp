@@ -3,11 +3,13 @@
 //
 // One scheduling thread owns all device work of a server.  A step is a replay
 // of an instantiated graph (step-table upload, then the whole-graph and the
-// streamed step kernels side by side) followed by a host callback; two step
-// tables alternate so the thread can queue step k+1 while
-// step k runs (stream order keeps every request's stages in sequence).  The
-// callback, which must not call HIP, only marks the requests that finished in
-// its step and wakes the thread.
+// streamed step kernels side by side) on the work stream, followed by an
+// event; a host callback on a second stream waits for that event, so the
+// callback never stands between two steps on the work stream.  Two step
+// tables alternate so the thread can queue step k+1 while step k runs (stream
+// order keeps every request's stages in sequence).  The callback, which must
+// not call HIP, only marks the requests that finished in its step and wakes
+// the thread.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -60,6 +62,7 @@ struct StepBuf {
     StepTable *d_tab = nullptr;
     hipGraphExec_t exec = nullptr;         // rational-factor sections
     hipGraphExec_t exec_lookup = nullptr;  // all four sections
+    hipEvent_t done = nullptr;             // recorded on the work stream after the step's graph
     bool busy = false;
     bool lookup = false;               // the step has lookup-factor work (replay exec_lookup)
     std::vector<Request *> finishing;  // requests whose last stage is in this step
@@ -95,10 +98,12 @@ struct Server : cos_server {
     int inflight = 0;
     cos_server_stats st{};
     // device
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // every step, set-up copy and fill, in order
+    hipStream_t cb_stream = nullptr;  // completion callbacks, each after its step's event, so that a
+                                      // callback never holds back the next step on the work stream
     char *d_arena = nullptr;
     ServeReqDev *d_reqs = nullptr;
-    ServeReqDev *h_reqs = nullptr;  // pinned staging, one entry per slot
+    std::vector<StepSetup> pending_setup;  // set-up of admitted requests not yet carried by a step
     StepBuf bufs[2];
     std::thread worker;
 
@@ -108,7 +113,7 @@ struct Server : cos_server {
 
     ~Server();
     void run();
-    hipError_t setup(Request *r);
+    StepSetup setup_entry(const Request *r) const;
     void fail_request(Request *r);
 };
 
@@ -177,11 +182,14 @@ uint32_t stage_items(const Request &r, int stage, uint32_t *n_rg, uint32_t *kind
     return static_cast<uint32_t>((r.S + kServeCombineTile - 1) / kServeCombineTile);
 }
 
-// Upload a newly admitted request's slot entry and clear its exponent rows.
-hipError_t Server::setup(Request *r) {
+// A newly admitted request's slot entry and exponent-row initial value (host
+// only: the set-up kernel of the first step that includes the request writes
+// them on the device).
+StepSetup Server::setup_entry(const Request *r) const {
     const Graph &g = *r->g;
-    ServeReqDev &d = h_reqs[r->slot];
-    d = ServeReqDev{};
+    StepSetup su{};
+    su.slot = static_cast<uint32_t>(r->slot);
+    ServeReqDev &d = su.req;
     d.row_ptr = g.d_row_ptr;
     d.edges = g.d_edges;
     d.edges32 = g.d_edges32;
@@ -206,17 +214,14 @@ hipError_t Server::setup(Request *r) {
     d.t32 = r->table32 ? reinterpret_cast<float *>(d.ws + r->wlay.off_table32) : nullptr;
     d.off_red = static_cast<uint32_t>(r->flay.off_red);
     d.off_part = static_cast<uint32_t>(r->flay.off_part);
-    hipError_t err = hipMemcpyAsync(d_reqs + r->slot, &d, sizeof(ServeReqDev), hipMemcpyHostToDevice, stream);
     // exponent rows: row 0 holds level 1's headroom 2^h_1 (binary16; else 0 = no
     // shift), rows 1..L start at zero for the levels' maxima
-    if (err == hipSuccess && !r->fused && is_rescaled(r->p)) {
-        uint32_t *rows = reinterpret_cast<uint32_t *>(d.ws + d.off_maxbits);
+    if (!r->fused && is_rescaled(r->p)) {
         const int32_t h1 = r->p == COS_FP16_RESCALED && g.L >= 2 ? g.h16[1] : 0;
-        err = launch_fill_u32(rows, h1 ? static_cast<uint32_t>(127 + h1) << 23 : 0u, r->wlay.S_pad, stream);
-        if (err == hipSuccess)
-            err = launch_fill_u32(rows + r->wlay.S_pad, 0u, static_cast<int64_t>(g.L) * r->wlay.S_pad, stream);
+        su.fill = 1;
+        su.row0 = h1 ? static_cast<uint32_t>(127 + h1) << 23 : 0u;
     }
-    return err;
+    return su;
 }
 
 // Mark an active request failed and give back its slot and workspace (under the lock).
@@ -243,22 +248,19 @@ void Server::run() {
             admission_index.push_back(admissions++);
         }
 
-        // ---- slot entries of the admitted requests (device actions without the lock; stream order puts
-        // them before the step that first reads them).  A request whose set-up fails fails alone.
+        // ---- set-up of the admitted requests (slot entry, exponent rows), carried by the next step, which
+        // is the first to include them.  A request whose set-up fails fails alone.
         if (!admitted.empty()) {
-            const int64_t inject = fail_admission_at;
-            lk.unlock();
-            std::vector<Request *> failed;
+            bool failed = false;
             for (size_t i = 0; i < admitted.size(); ++i) {
-                Request *r = admitted[i];
-                const hipError_t err = admission_index[i] == inject ? hipErrorUnknown : setup(r);
-                if (err != hipSuccess)
-                    failed.push_back(r);
+                if (admission_index[i] == fail_admission_at) {
+                    fail_request(admitted[i]);
+                    failed = true;
+                } else {
+                    pending_setup.push_back(setup_entry(admitted[i]));
+                }
             }
-            lk.lock();
-            for (Request *r : failed)
-                fail_request(r);
-            if (!failed.empty())
+            if (failed)
                 cv.notify_all();
         }
         int active = 0;
@@ -291,6 +293,9 @@ void Server::run() {
                 if (r->next_stage + 1 == r->n_stages)
                     b->finishing.push_back(r);
             });
+            t.n_setup = static_cast<uint32_t>(pending_setup.size());
+            std::copy(pending_setup.begin(), pending_setup.end(), t.setup);
+            pending_setup.clear();
             int64_t all_items = 0;
             for (int sec = 0; sec < SS_COUNT; ++sec) {
                 t.n[sec] = count[sec];
@@ -333,13 +338,19 @@ void Server::run() {
             err = hipGraphLaunch(b->lookup ? b->exec_lookup : b->exec, stream);
         }
         if (err == hipSuccess)
-            err = hipLaunchHostFunc(stream, step_done, b);
+            err = hipEventRecord(b->done, stream);
+        if (err == hipSuccess)
+            err = hipStreamWaitEvent(cb_stream, b->done, 0);
+        if (err == hipSuccess)
+            err = hipLaunchHostFunc(cb_stream, step_done, b);
         lk.lock();
         if (err != hipSuccess) {
-            // the device is unusable for this server: fail every active request
+            // the device is unusable for this server: fail every active request (set-ups not yet
+            // carried by a step belong to them)
             for (Request *r : slots)
                 if (r)
                     fail_request(r);
+            pending_setup.clear();
             b->finishing.clear();
             b->busy = false;
             --inflight;
@@ -358,15 +369,17 @@ Server::~Server() {
             (void)hipFree(b.d_tab);
         if (b.h_tab)
             (void)hipHostFree(b.h_tab);
+        if (b.done)
+            (void)hipEventDestroy(b.done);
     }
     if (d_reqs)
         (void)hipFree(d_reqs);
-    if (h_reqs)
-        (void)hipHostFree(h_reqs);
     if (d_arena)
         (void)hipFree(d_arena);
     if (stream)
         (void)hipStreamDestroy(stream);
+    if (cb_stream)
+        (void)hipStreamDestroy(cb_stream);
 }
 
 Server *server_of(cos_server *s) { return static_cast<Server *>(s); }
@@ -392,19 +405,20 @@ extern "C" cos_status cos_server_create(uint64_t hbm_budget, int32_t max_slots, 
         hipError_t err = hipGetDevice(&s->device);
         if (err == hipSuccess)
             err = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (err == hipSuccess)
+            err = hipStreamCreateWithFlags(&s->cb_stream, hipStreamNonBlocking);
         if (err == hipSuccess && hbm_budget)
             err = hipMalloc(reinterpret_cast<void **>(&s->d_arena), hbm_budget);
         if (err == hipSuccess)
             err = hipMalloc(reinterpret_cast<void **>(&s->d_reqs), sizeof(ServeReqDev) * max_slots);
-        if (err == hipSuccess)
-            err = hipHostMalloc(reinterpret_cast<void **>(&s->h_reqs), sizeof(ServeReqDev) * max_slots,
-                                hipHostMallocDefault);
         for (StepBuf &b : s->bufs) {
             b.srv = s.get();
             if (err == hipSuccess)
                 err = hipHostMalloc(reinterpret_cast<void **>(&b.h_tab), sizeof(StepTable), hipHostMallocDefault);
             if (err == hipSuccess)
                 err = hipMalloc(reinterpret_cast<void **>(&b.d_tab), sizeof(StepTable));
+            if (err == hipSuccess)
+                err = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
             if (err == hipSuccess)
                 err = serve_build_step_graph(b.d_tab, b.h_tab, s->d_reqs, false, &b.exec);
             if (err == hipSuccess)
@@ -624,6 +638,9 @@ extern "C" cos_status cos_server_destroy(cos_server *h) {
     if (s->worker.joinable())
         s->worker.join();
     hipError_t err = hipStreamSynchronize(s->stream);
+    const hipError_t cb_err = hipStreamSynchronize(s->cb_stream);
+    if (err == hipSuccess)
+        err = cb_err;
     delete s;
     if (err != hipSuccess)
         return hip_fail(err, "cos_server_destroy");
