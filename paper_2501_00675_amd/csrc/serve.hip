@@ -200,16 +200,28 @@ __global__ __launch_bounds__(kFusedThreads) void serve_fused_kernel(const StepTa
 // SS_STREAMED_LOOKUP with KIND lookup, where the binary32 precisions read the
 // binary32 copy of the tables made by the request's first stage).
 template <int KIND, uint32_t SEC>
-__global__ __launch_bounds__(kBlock) void serve_stream_kernel(const StepTable *__restrict__ tab,
+__global__ __launch_bounds__(kBlock) void serve_stream_kernel(StepTable *__restrict__ tab,
                                                               const ServeReqDev *__restrict__ reqs) {
     __shared__ __align__(16) unsigned char lds[4 * kWave * kServeLevelK * sizeof(uint32_t)];
+    __shared__ uint32_t claim;
     static_assert(sizeof(lds) >= 4 * kWave * kServeFinalK * sizeof(double), "final-node staging");
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lo = section_begin(*tab, SEC);
     const uint32_t n = tab->n[SEC];
     const uint32_t total = tab->items[SEC];
-    for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    // items cost different amounts (they belong to different requests), so a
+    // workgroup claims its next item when it is done with the last: items
+    // c, c + 8, c + 16, ... from the counter of c = the workgroup's XCD (eight
+    // counters, so that claims do not all serialise on one address)
+    const uint32_t c = blockIdx.x % kXcds;
+    for (;;) {
+        if (threadIdx.x == 0)
+            claim = c + kXcds * atomicAdd(&tab->claimed[SEC][c].v, 1u);
+        __syncthreads();
+        const uint32_t item = claim;
+        if (item >= total)
+            break;
         const StepEntry &en = tab->e[find_entry(tab, lo, n, item)];
         const ServeReqDev &r = reqs[en.slot];
         const uint32_t local = item - en.item_base;

@@ -77,8 +77,13 @@ struct StepSetup {
 struct StepTable {
     uint32_t n[SS_COUNT];      // entries per section
     uint32_t items[SS_COUNT];  // items per section
-    uint32_t n_setup;          // newly admitted requests whose set-up this step carries
+    uint32_t n_setup;            // newly admitted requests whose set-up this step carries
     uint32_t pad[3];
+    // item counters of the streamed sections, one per XCD and section, a cache
+    // line each (uploaded as 0 with the table)
+    struct alignas(128) Counter {
+        uint32_t v;
+    } claimed[SS_COUNT][kXcds];
     StepEntry e[kServeMaxEntries];
     StepSetup setup[kServeMaxEntries];
 };

@@ -293,6 +293,9 @@ void Server::run() {
                 if (r->next_stage + 1 == r->n_stages)
                     b->finishing.push_back(r);
             });
+            for (auto &per_section : t.claimed)
+                for (auto &c : per_section)
+                    c.v = 0;
             t.n_setup = static_cast<uint32_t>(pending_setup.size());
             std::copy(pending_setup.begin(), pending_setup.end(), t.setup);
             pending_setup.clear();
