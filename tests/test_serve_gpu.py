@@ -110,6 +110,40 @@ def test_mix_bit_identical_to_evaluate_and_alone(P):
         assert_parity(outs[i][idx], V, Q, j["precision"], f"mix request {i}")
 
 
+def test_large_admission_batches_carry_their_set_up(P):
+    # 512 slots: a long request keeps the steps busy while 600 small ones are submitted, so the
+    # scheduler admits them in large batches whose set-up (slot entries; exponent rows of the
+    # streamed rescaled ones) rides on one step each.  Every result must equal cos_evaluate's bits.
+    gb, xb = make_config("mid", S=3000, width=20000, L=8, degree=8, seed=52)
+    g1, _ = make_config("tiny", S=64)
+    g2, _ = make_config("mid", S=64, width=300, L=5, degree=3, seed=51)
+    Gb = P.Graph.from_leveled(gb)
+    Gs = [P.Graph.from_leveled(g1), P.Graph.from_leveled(g2).set_path("streamed")]
+    rng = np.random.default_rng(8)
+    jobs = [(i % 2, ("fp64", "fp32r", "bf16r", "fp16r")[i % 4], int(rng.integers(1, 200))) for i in range(600)]
+    xs = [rng.normal(size=(3, S)) for _, _, S in jobs]
+    refs = [gpu_eval(Gs[gi], x, p) for (gi, p, _), x in zip(jobs, xs)]
+    ref_b = gpu_eval(Gb, xb, "fp64")
+    xd = [to_dev(x) for x in xs]
+    xbd = to_dev(xb)
+    torch.cuda.synchronize()
+    say("serve 600 requests on 512 slots behind a long request")
+    with P.Server(2 << 30, 512) as srv:
+        gb_id = srv.add_graph(Gb)
+        gids = [srv.add_graph(G) for G in Gs]
+        tb = srv.submit(gb_id, xbd, "fp64", sync_inputs=False)
+        tickets = [srv.submit(gids[gi], x, p, sync_inputs=False) for (gi, p, _), x in zip(jobs, xd)]
+        stats = [srv.wait(t) for t in tickets]
+        sb = srv.wait(tb)
+    assert sb["status"] == 0 and all(st["status"] == 0 for st in stats)
+    assert np.array_equal(bits(tb.out.cpu().numpy()), bits(ref_b))
+    for i, (t, r) in enumerate(zip(tickets, refs)):
+        assert np.array_equal(bits(t.out.cpu().numpy()), bits(r)), f"request {i} {jobs[i]}"
+    batch = np.bincount([st["first_step"] for st in stats]).max()
+    say(f"largest batch of requests starting in one step: {batch}")
+    assert batch >= 32
+
+
 def test_lookup_graphs_served_bit_identical_alone_and_mixed(P):
     # lookup-factor graphs (a narrow one on the fused plan, a wide one streamed) share steps
     # with a rational graph; every result must equal cos_evaluate's bits.  Streamed lookup
