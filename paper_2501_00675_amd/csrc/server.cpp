@@ -300,7 +300,7 @@ void Server::run() {
             std::copy(pending_setup.begin(), pending_setup.end(), t.setup);
             pending_setup.clear();
             int64_t all_items = 0;
-            for (int sec = 0; sec < SS_COUNT; ++sec) {
+            for (uint32_t sec = 0; sec < SS_COUNT; ++sec) {
                 t.n[sec] = count[sec];
                 t.items[sec] = items[sec];
                 all_items += items[sec];
