@@ -257,6 +257,40 @@ def test_zero_in_degree_nodes_and_empty_level(P, precision):
     assert np.all(gpu_eval(graph(P, g3), x, precision) == 0.0)
 
 
+def _hub_graph(W, fan, rng):
+    # level 2 is a single node fed by all W nodes of level 1 (an interior in-degree of W), which
+    # then fans out to `fan` nodes; factors drawn as for the synthetic workloads
+    ar = np.arange(W)
+    widths = np.array([1, W, 1, fan, 1])
+    first = np.concatenate([[0], np.cumsum(widths)])
+    src = np.concatenate([np.zeros(W, int), first[1] + ar, np.full(fan, first[2]), first[3] + np.arange(fan)])
+    dst = np.concatenate([first[1] + ar, np.full(W, first[2]), first[3] + np.arange(fan), np.full(fan, first[4])])
+    E = len(src)
+    return LeveledGraph(widths, np.array([W, W, fan, fan]), src.astype(np.int32), dst.astype(np.int32),
+                        rng.uniform(-1, 1, E), rng.uniform(0.5, 2, E), rng.uniform(-1, 1, (E, 3)))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("W", [200, 4096])
+def test_interior_node_of_high_in_degree(P, precision, W):
+    # one wave sums the hub's W in-edges in order; the result must meet the bar, and where the
+    # graph fits the whole-graph plan both plans must give the same bits
+    rng = np.random.default_rng(W)
+    g = _hub_graph(W, 64, rng)
+    x = rng.uniform(-1, 1, (3, 300))
+    V, Q = oracle_ref(g, x)
+    G = graph(P, g)
+    say(f"hub in-degree {W} {precision}")
+    ys = gpu_eval(G.set_path("streamed"), x, precision)
+    assert_parity(ys, V, Q, precision, f"hub W={W}")
+    code = {"fp64": 0, "fp32r": 1, "fp32": 2}[precision]
+    if (G.info()["fused_mask"] >> code) & 1:
+        yf = gpu_eval(G.set_path("fused"), x, precision)
+        assert np.array_equal(yf.view(np.uint64), ys.view(np.uint64))
+    else:
+        assert W > 1000
+
+
 def test_transpose_agrees(P):
     g, x = make_config("mid", S=256, seed=9)
     y = gpu_eval(graph(P, g), x, "fp64")
