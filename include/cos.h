@@ -220,10 +220,12 @@ cos_status cos_evaluate_workspace_size(const cos_graph *g, int64_t S, cos_precis
  *                as out_dev[s] * 2^out_exp_dev[s] (for values whose magnitude
  *                may leave the binary64 range); always 0 for COS_FP64.
  *   workspace_dev, workspace_bytes
- *                device scratch of at least cos_evaluate_workspace_size bytes,
- *                256-byte aligned, used only by work queued on `stream`.
- *                NULL: the library allocates and frees it in stream order
- *                (hipMallocAsync / hipFreeAsync).
+ *                device scratch, 256-byte aligned, used only by work queued
+ *                on `stream`: cos_evaluate_workspace_size bytes, or on the
+ *                streamed plan less (room for at least 256 samples), in which
+ *                case the sweep runs in sample chunks that fit it (the same
+ *                results).  NULL: the library allocates and frees it in
+ *                stream order (hipMallocAsync / hipFreeAsync).
  *   stream       hipStream_t as void*.
  *
  * Asynchronous: returns once the work is queued.  With a workspace it queues
