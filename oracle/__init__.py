@@ -4,7 +4,8 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library and the library
 never calls it.
 
-  level_sweep.c  plain FP64 level-by-level evaluator (C, OpenMP over samples)
+  level_sweep.c  plain FP64 level-by-level evaluator (C, OpenMP over samples);
+                 built a second time with long double arithmetic as a self-check
   path_sum.py    the definition itself: exact rational sum over all paths
   mc.py          the Metropolis chain over sample configurations, with its
                  counter-based generator (Philox4x64-10), step by step
@@ -24,7 +25,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "level_sweep.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_LD = os.path.join(_HERE, "liboracle_ld.so")
 _lib = None
+_lib_ld = None
 
 MODES = {"value": 0, "abs": 1, "square": 2}
 
@@ -43,6 +46,11 @@ def build(out: str = _LIB, src: str = _SRC, defines: tuple = ()) -> str:
     with open(out + ".srchash", "w") as f:
         f.write(_src_hash(src))
     return out
+
+
+def build_long_double(out: str = _LIB_LD) -> str:
+    """The self-check build of level_sweep.c: the same sweep carried in long double (x87 80-bit)."""
+    return build(out, defines=("-DORACLE_LONG_DOUBLE",))
 
 
 def _bind(lib):
@@ -87,6 +95,26 @@ def load(path: str = _LIB, rebuild_if_stale: bool = True):
         if lib.oracle_src_hash().decode() != _src_hash():
             raise ImportError(f"{path} was built from other sources; rebuild with oracle.build()")
         _lib = lib
+    return lib
+
+
+def load_long_double():
+    """The self-check build (every factor, product and sum in long double), built when missing or
+    out of date.  Same entry points as load(); results are rounded to binary64 on output."""
+    global _lib_ld
+    if _lib_ld is not None:
+        return _lib_ld
+    try:
+        with open(_LIB_LD + ".srchash") as f:
+            stale = f.read().strip() != _src_hash()
+    except OSError:
+        stale = True
+    if stale or not os.path.exists(_LIB_LD):
+        build_long_double()
+    lib = _bind(ctypes.CDLL(_LIB_LD))
+    if lib.oracle_src_hash().decode() != _src_hash():
+        raise ImportError(f"{_LIB_LD} was built from other sources; rebuild with oracle.build_long_double()")
+    _lib_ld = lib
     return lib
 
 

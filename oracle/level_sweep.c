@@ -34,6 +34,13 @@
  * The *_nodes entry points also return the value every node holds after the
  * sweep (the sum over root-to-node paths), for every sample.
  *
+ * Self-check build (-DORACLE_LONG_DOUBLE): the same sweep with every factor,
+ * product and sum carried in long double (x87 80-bit, 64-bit significand),
+ * rounded to binary64 only when the final or node values are written out.  It
+ * bounds the binary64 oracle's own rounding error (Sec. III, numerical
+ * stability: how far a lower precision drifts from a higher one), which is
+ * what the error metric of the parity tests is calibrated against.
+ *
  * Parity pins: brute-force exact path sums, closed forms, transpose invariance
  * and exact power-of-two scaling (see the oracle tests).
  */
@@ -54,6 +61,15 @@
 #define ORACLE_ENOMEM 2
 
 #define SAMPLE_BLOCK 8
+
+/* Arithmetic type of the sweep (binary64 unless the self-check build). */
+#ifdef ORACLE_LONG_DOUBLE
+typedef long double real;
+#define REAL_ABS fabsl
+#else
+typedef double real;
+#define REAL_ABS fabs
+#endif
 
 const char *oracle_src_hash(void) { return ORACLE_SRC_HASH; }
 
@@ -131,13 +147,13 @@ int oracle_check_lookup(int32_t L, const int64_t *widths, const int64_t *epl,
 }
 
 /* The edge factor, literally as defined. */
-static double edge_factor(double a, double b, const double *k, double x0, double x1, double x2)
+static real edge_factor(real a, real b, const double *k, real x0, real x1, real x2)
 {
-    double d0 = x0 - k[0];
-    double d1 = x1 - k[1];
-    double d2 = x2 - k[2];
-    double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-    return a / (1.0 + b * r2);
+    real d0 = x0 - (real)k[0];
+    real d1 = x1 - (real)k[1];
+    real d2 = x2 - (real)k[2];
+    real r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    return a / ((real)1.0 + b * r2);
 }
 
 /*
@@ -187,13 +203,13 @@ static int sweep(int32_t kind, int32_t L, const int64_t *widths, const int64_t *
 #endif
         /* value[node * SAMPLE_BLOCK + j] for every node of the graph,
            allocated when this thread receives its first block */
-        double *value = NULL;
+        real *value = NULL;
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
         for (int64_t blk = 0; blk < n_blocks; ++blk) {
             if (!value)
-                value = (double *)malloc(sizeof(double) * (size_t)n_nodes * SAMPLE_BLOCK);
+                value = (real *)malloc(sizeof(real) * (size_t)n_nodes * SAMPLE_BLOCK);
             if (!value) {
 #ifdef _OPENMP
 #pragma omp atomic write
@@ -215,13 +231,13 @@ static int sweep(int32_t kind, int32_t L, const int64_t *widths, const int64_t *
                 for (int64_t e = edge_first[l - 1]; e < edge_first[l]; ++e) {
                     for (int64_t j = 0; j < nb; ++j) {
                         int64_t s = s0 + j;
-                        double w;
+                        real w;
                         if (kind == 0)
                             w = edge_factor(a[e], b[e], &k[3 * e], x[s], x[S + s], x[2 * S + s]);
                         else
-                            w = coef[e] * x[(int64_t)slot[e] * S + s];
+                            w = (real)coef[e] * (real)x[(int64_t)slot[e] * S + s];
                         if (mode == 1)
-                            w = fabs(w);
+                            w = REAL_ABS(w);
                         else if (mode == 2)
                             w = w * w;
                         value[(int64_t)dst[e] * SAMPLE_BLOCK + j] += w * value[(int64_t)src[e] * SAMPLE_BLOCK + j];
@@ -229,11 +245,11 @@ static int sweep(int32_t kind, int32_t L, const int64_t *widths, const int64_t *
                 }
             }
             for (int64_t j = 0; j < nb; ++j)
-                out[s0 + j] = value[final_node * SAMPLE_BLOCK + j];
+                out[s0 + j] = (double)value[final_node * SAMPLE_BLOCK + j];
             if (nodes)
                 for (int64_t n = 0; n < n_nodes; ++n)
                     for (int64_t j = 0; j < nb; ++j)
-                        nodes[n * S + s0 + j] = value[n * SAMPLE_BLOCK + j];
+                        nodes[n * S + s0 + j] = (double)value[n * SAMPLE_BLOCK + j];
         }
         free(value);
     }
