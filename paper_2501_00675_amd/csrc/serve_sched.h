@@ -68,14 +68,24 @@ class Arena {
     std::list<std::pair<uint64_t, uint64_t>> free_;  // (offset, bytes), sorted by offset
 };
 
+// How many later requests may be admitted ahead of a queued request whose
+// workspace does not fit yet.
+constexpr int kMaxBypass = 32;
+
 // Admit queued requests in order while a slot is free: a request whose
 // workspace (footprint bytes, 0 for none) does not fit in the arena now stays
-// queued without blocking the ones behind it.  Admitted requests get a slot
-// (the lowest free) and arena_off; returns them in admission order.
-// Req needs: footprint, arena_off, slot.
+// queued without blocking the ones behind it -- but only until max_bypass
+// later requests have been admitted ahead of it (its bypassed count).  From
+// then on admission stops at it until its workspace fits, which the
+// completion of active requests guarantees (every footprint fits the whole
+// arena), so no request waits without bound behind a stream of smaller ones.
+// Admitted requests get a slot (the lowest free) and arena_off; returns them
+// in admission order.  Req needs: footprint, arena_off, slot, bypassed.
 template <class Req>
-std::vector<Req *> admit(std::deque<Req *> &queue, std::vector<Req *> &slots, Arena &arena) {
+std::vector<Req *> admit(std::deque<Req *> &queue, std::vector<Req *> &slots, Arena &arena,
+                         int max_bypass = kMaxBypass) {
     std::vector<Req *> admitted;
+    std::vector<Req *> waiting;  // requests passed over in this call
     int free_slots = 0;
     for (Req *r : slots)
         free_slots += r == nullptr;
@@ -83,6 +93,9 @@ std::vector<Req *> admit(std::deque<Req *> &queue, std::vector<Req *> &slots, Ar
         Req *r = *it;
         uint64_t off = 0;
         if (r->footprint && !arena.alloc(r->footprint, &off)) {
+            if (r->bypassed >= max_bypass)
+                break;  // its turn: nothing behind it goes first
+            waiting.push_back(r);
             ++it;
             continue;
         }
@@ -92,6 +105,11 @@ std::vector<Req *> admit(std::deque<Req *> &queue, std::vector<Req *> &slots, Ar
         --free_slots;
         admitted.push_back(r);
         it = queue.erase(it);
+        bool hold = false;
+        for (Req *w : waiting)
+            hold |= ++w->bypassed >= max_bypass;
+        if (hold)
+            break;
     }
     return admitted;
 }

@@ -36,6 +36,7 @@ enum ReqState { RS_QUEUED, RS_ACTIVE, RS_DONE, RS_CANCELED, RS_FAILED };
 
 struct Request {
     uint64_t ticket = 0;
+    int bypassed = 0;  // later requests admitted ahead of this one (admit bounds it)
     const Graph *g = nullptr;
     const double *x = nullptr;
     double *out = nullptr;
@@ -472,6 +473,8 @@ extern "C" cos_status cos_server_submit(cos_server *h, int32_t gid, const double
     }
     const Graph &g = *r->g;
     // the conditions cos_evaluate refuses for 16-bit storage
+    if (check_precision_range(g, p, "cos_server_submit") != COS_OK)
+        return COS_EINVAL;
     if (value_bytes(p) == 2 && g.path == COS_PATH_FUSED)
         return fail(COS_EINVAL, "cos_server_submit: 16-bit level storage runs on the streamed plan only");
     if (p == COS_FP16_RESCALED && g.h16.empty())

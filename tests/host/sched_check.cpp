@@ -21,6 +21,7 @@ struct FakeReq {
     bool fused = false;
     int section = 0;  // 0 / 2: whole-graph work, 1 / 3: streamed work (rational / lookup factors)
     int next_stage = 0, n_stages = 0;
+    int bypassed = 0;
     int admitted_step = -1, done_step = -1;
     int last_stage_step = -1;
     bool cancelled = false;
@@ -114,16 +115,21 @@ static void simulate(uint32_t seed, int n_req, int max_slots, uint64_t budget) {
             sum += kv.second;
         }
         CHECK(end <= budget && sum == arena.used(), "arena accounting");
-        // a request not admitted while a slot was free must not fit in the largest free block
+        // a request not admitted while a slot was free must not fit in the largest free block,
+        // unless an earlier request that does not fit has been passed over kMaxBypass times
         if (active < max_slots) {
             uint64_t largest = 0;
             for (auto &b : arena.free_blocks())
                 largest = std::max(largest, b.second);
             for (FakeReq *q : queue) {
                 const bool fits = q->footprint == 0 || Arena::granules(q->footprint) <= largest;
+                if (!fits && q->bypassed >= kMaxBypass)
+                    break;
                 CHECK(!fits, "request %d fits but was not admitted", q->id);
             }
         }
+        for (FakeReq *q : queue)
+            CHECK(q->bypassed <= kMaxBypass, "request %d passed over %d times", q->id, q->bypassed);
         // compose and run one step
         if (!any_stage_left(slots))
             continue;
@@ -155,10 +161,67 @@ static void simulate(uint32_t seed, int n_req, int max_slots, uint64_t budget) {
     CHECK(arena.used() == 0 && arena.free_blocks().size() == 1, "arena not fully coalesced at the end");
     for (FakeReq &r : reqs)
         CHECK(r.cancelled || r.done_step >= 0, "request %d never finished", r.id);
+    // counted independently of admit(): later requests admitted before each request
+    for (FakeReq &r : reqs) {
+        if (r.cancelled)
+            continue;
+        int ahead = 0;
+        for (FakeReq &q : reqs)
+            ahead += q.id > r.id && !q.cancelled && q.admitted_step < r.admitted_step;
+        CHECK(ahead <= kMaxBypass && ahead == r.bypassed, "request %d: %d later requests went first (count %d)",
+              r.id, ahead, r.bypassed);
+    }
+}
+
+// A large request queued behind a steady stream of small ones that each live two
+// steps: without a bound the arena never has room for it; with it, the small ones
+// stop after kMaxBypass admissions ahead of it, drain, and it is admitted.
+static void bypass_unit() {
+    const uint64_t G = Arena::kGranule;
+    Arena arena(10 * G);
+    std::vector<FakeReq *> slots(4, nullptr);
+    std::deque<FakeReq *> queue;
+    std::vector<FakeReq> reqs(400);
+    FakeReq &big = reqs[0];
+    big.id = 0;
+    big.footprint = 9 * G;
+    std::vector<std::pair<FakeReq *, int>> live;  // (request, retire step)
+    FakeReq first;
+    first.footprint = 2 * G;
+    std::deque<FakeReq *> q0{&first};
+    admit(q0, slots, arena);
+    live.push_back({&first, 1});
+    queue.push_back(&big);
+    int next = 1, big_step = -1;
+    for (int step = 0; step < 200 && big_step < 0; ++step) {
+        if (next < static_cast<int>(reqs.size())) {  // one small arrival per step
+            reqs[next].id = next;
+            reqs[next].footprint = G;
+            queue.push_back(&reqs[next++]);
+        }
+        for (FakeReq *r : admit(queue, slots, arena)) {
+            if (r == &big)
+                big_step = step;
+            else
+                live.push_back({r, step + 2});
+        }
+        for (auto it = live.begin(); it != live.end();) {
+            if (it->second == step) {
+                arena.release(it->first->arena_off, it->first->footprint);
+                slots[it->first->slot] = nullptr;
+                it = live.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    CHECK(big_step >= 0, "the large request was never admitted");
+    CHECK(big.bypassed == kMaxBypass, "the large request was passed over %d times", big.bypassed);
 }
 
 int main() {
     arena_unit();
+    bypass_unit();
     simulate(1, 400, 8, 1 << 20);
     simulate(2, 400, 64, 1 << 22);
     simulate(3, 300, 1, 1 << 16);   // one slot: strictly one request at a time

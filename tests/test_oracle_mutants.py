@@ -14,24 +14,25 @@ import pins
 
 MUTANTS = {
     "dropped_last_edge": ("e < edge_first[l]; ++e", "e < edge_first[l] - 1; ++e"),
-    "factor_sign": ("return a / (1.0 + b * r2);", "return -a / (1.0 + b * r2);"),
-    "offset_sign": ("double d1 = x1 - k[1];", "double d1 = x1 + k[1];"),
+    "factor_sign": ("return a / ((real)1.0 + b * r2);", "return -a / ((real)1.0 + b * r2);"),
+    "offset_sign": ("real d1 = x1 - (real)k[1];", "real d1 = x1 + (real)k[1];"),
     "sample_index": ("x[S + s]", "x[s]"),
-    "k_component": ("double d2 = x2 - k[2];", "double d2 = x2 - k[1];"),
-    "swapped_a_b": ("return a / (1.0 + b * r2);", "return b / (1.0 + a * r2);"),
+    "k_component": ("real d2 = x2 - (real)k[2];", "real d2 = x2 - (real)k[1];"),
+    "swapped_a_b": ("return a / ((real)1.0 + b * r2);", "return b / ((real)1.0 + a * r2);"),
     "reads_dst_value": ("+= w * value[(int64_t)src[e]", "+= w * value[(int64_t)dst[e]"),
-    "missing_square_norm": ("w = w * w;", "w = fabs(w);"),
-    "r_not_squared": ("return a / (1.0 + b * r2);", "return a / (1.0 + b * sqrt(r2));"),
+    "missing_square_norm": ("w = w * w;", "w = REAL_ABS(w);"),
+    "r_not_squared": ("return a / ((real)1.0 + b * r2);", "return a / ((real)1.0 + b * sqrt(r2));"),
     "root_not_one": ("value[0 * SAMPLE_BLOCK + j] = 1.0;", "value[0 * SAMPLE_BLOCK + j] = 2.0;"),
     "level_not_cleared": ("value[n * SAMPLE_BLOCK + j] = 0.0;", "value[n * SAMPLE_BLOCK + j] = 1.0;"),
     # lookup factors
-    "lookup_constant_dropped": ("w = coef[e] * x[(int64_t)slot[e] * S + s];", "w = x[(int64_t)slot[e] * S + s];"),
-    "lookup_wrong_slot": ("w = coef[e] * x[(int64_t)slot[e] * S + s];",
-                          "w = coef[e] * x[(int64_t)(slot[e] > 0 ? slot[e] - 1 : 0) * S + s];"),
-    "lookup_wrong_sample": ("w = coef[e] * x[(int64_t)slot[e] * S + s];",
-                            "w = coef[e] * x[(int64_t)slot[e] * S + s0];"),
-    "lookup_constant_squared": ("w = coef[e] * x[(int64_t)slot[e] * S + s];",
-                                "w = coef[e] * coef[e] * x[(int64_t)slot[e] * S + s];"),
+    "lookup_constant_dropped": ("w = (real)coef[e] * (real)x[(int64_t)slot[e] * S + s];",
+                                "w = (real)x[(int64_t)slot[e] * S + s];"),
+    "lookup_wrong_slot": ("w = (real)coef[e] * (real)x[(int64_t)slot[e] * S + s];",
+                          "w = (real)coef[e] * (real)x[(int64_t)(slot[e] > 0 ? slot[e] - 1 : 0) * S + s];"),
+    "lookup_wrong_sample": ("w = (real)coef[e] * (real)x[(int64_t)slot[e] * S + s];",
+                            "w = (real)coef[e] * (real)x[(int64_t)slot[e] * S + s0];"),
+    "lookup_constant_squared": ("w = (real)coef[e] * (real)x[(int64_t)slot[e] * S + s];",
+                                "w = (real)coef[e] * (real)coef[e] * (real)x[(int64_t)slot[e] * S + s];"),
 }
 
 
