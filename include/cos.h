@@ -133,7 +133,9 @@ int32_t cos_abi_version(void);
  *                     dst in level l.  Any order within a level; parallel
  *                     edges are separate terms; nodes without in-edges hold 0.
  *   a, b     host     float64[E]: finite, b >= 0 (b = 0 gives w = a).
- *   k        host     float64[E][3], finite.
+ *   k        host     float64[E][3], finite; 1 + b|k|^2 and 2b|k_i| must be
+ *                     finite in binary64 (the library evaluates the
+ *                     denominator in the expanded form c0 + b|x|^2 + g.x).
  *   out               receives the handle; release with cos_destroy_graph.
  *
  * The inputs are copied; the caller may free them on return.  Within each
@@ -232,7 +234,9 @@ cos_status cos_evaluate_workspace_size(const cos_graph *g, int64_t S, cos_precis
  * kernel launches only (no allocation, no memset), so it may be captured into
  * a HIP graph on `stream` and replayed; replays read x and write out afresh.
  * Errors: COS_EINVAL (NULL or misaligned pointers, bad S or precision,
- * workspace too small), COS_ENOMEM, COS_EDEVICE (launch failure).
+ * workspace too small, a binary32 precision for a graph with a parameter
+ * (a, b, k or coef) that rounds to infinity in binary32), COS_ENOMEM,
+ * COS_EDEVICE (launch failure).
  */
 cos_status cos_evaluate(const cos_graph *g, const double *x_dev, int64_t S, cos_precision p,
                         double *out_dev, int32_t *out_exp_dev, void *workspace_dev,

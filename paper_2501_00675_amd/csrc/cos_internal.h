@@ -95,6 +95,10 @@ struct Graph {
     // binary16 storage: headroom exponent h[l] of node level l = 1..L-1
     // (h[0] unused); empty when the graph's factors have no bound (lookup)
     std::vector<int32_t> h16;
+    // whether every binary32 record field is finite: a finite binary64
+    // parameter beyond the binary32 range rounds to +-inf, and the binary32
+    // sweeps then refuse the graph
+    bool f32_ok = true;
     // canonical host copy (for export)
     std::vector<int32_t> h_src, h_dst;
     std::vector<double> h_a, h_b, h_k;       // rational factors
@@ -114,6 +118,10 @@ struct Graph {
 };
 
 const Graph &graph_of(const cos_graph *h);
+// COS_OK if the graph's records can be evaluated at precision p, else the
+// refusal (COS_EINVAL, message prefixed with who): binary32 sweeps need every
+// binary32 record field finite.
+cos_status check_precision_range(const Graph &g, cos_precision p, const char *who);
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string &msg);

@@ -130,6 +130,8 @@ extern "C" cos_status cos_evaluate(const cos_graph *h, const double *x_dev, int6
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != g.device)
         return fail(COS_EINVAL, "cos_evaluate: the current device is not the graph's device");
+    if (check_precision_range(g, p, "cos_evaluate") != COS_OK)
+        return COS_EINVAL;
     if (value_bytes(p) == 2 && g.path == COS_PATH_FUSED)
         return fail(COS_EINVAL, "cos_evaluate: 16-bit level storage runs on the streamed plan only");
     if (p == COS_FP16_RESCALED && g.h16.empty())

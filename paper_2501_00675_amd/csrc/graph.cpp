@@ -252,6 +252,14 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
                        !std::isfinite(P.k[3 * e]) || !std::isfinite(P.k[3 * e + 1]) ||
                        !std::isfinite(P.k[3 * e + 2])) {
                 return fail(COS_EINVAL, "edge " + std::to_string(e) + ": parameters must be finite with b >= 0");
+            } else {
+                // the expanded binary64 denominator c0 + b|x|^2 + g.x (c0 = 1 + b|k|^2,
+                // g = -2bk) is what the binary64 sweep and every final node evaluate:
+                // its coefficients must be finite
+                const double b = P.b[e], k0 = P.k[3 * e], k1 = P.k[3 * e + 1], k2 = P.k[3 * e + 2];
+                if (!std::isfinite(1.0 + b * (k0 * k0 + k1 * k1 + k2 * k2)) || !std::isfinite(2.0 * b * k0) ||
+                    !std::isfinite(2.0 * b * k1) || !std::isfinite(2.0 * b * k2))
+                    return fail(COS_EINVAL, "edge " + std::to_string(e) + ": 1 + b|k|^2 or 2bk overflows binary64");
             }
         }
     }
@@ -350,6 +358,7 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
                 EdgeRecL &rl = recsL[q];
                 rl.coef = G.h_coef[q];
                 rl.coef32 = static_cast<float>(G.h_coef[q]);
+                G.f32_ok = G.f32_ok && std::isfinite(rl.coef32);
                 rl.slot = G.h_slot[q];
                 rl.src = src_local;
                 continue;
@@ -370,6 +379,8 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
             r32.k1 = static_cast<float>(k1);
             r32.k2 = static_cast<float>(k2);
             r32.src = src_local;
+            G.f32_ok = G.f32_ok && std::isfinite(r32.a) && std::isfinite(r32.b) && std::isfinite(r32.k0) &&
+                       std::isfinite(r32.k1) && std::isfinite(r32.k2);
         }
         // row boundaries inside the edge stream: the last edge of every
         // non-empty row, and how many empty rows follow it
@@ -545,4 +556,11 @@ extern "C" cos_status cos_destroy_graph(cos_graph *h) {
 // accessor for the other translation units
 namespace cosdag {
 const Graph &graph_of(const cos_graph *h) { return h->g; }
+
+cos_status check_precision_range(const Graph &g, cos_precision p, const char *who) {
+    if (p != COS_FP64 && !g.f32_ok)
+        return fail(COS_EINVAL, std::string(who) + ": an edge parameter lies beyond the binary32 range (it rounds "
+                                                   "to infinity); evaluate this graph with COS_FP64");
+    return COS_OK;
+}
 }  // namespace cosdag

@@ -95,6 +95,8 @@ extern "C" cos_status cos_mc_run(const cos_graph *h, cos_precision p, int64_t C,
     if (g.kind != FK_RATIONAL)
         return fail(COS_EINVAL, "cos_mc_run: the walkers move coordinates x, so the graph needs rational factors");
     // the conditions cos_evaluate would refuse inside the loop, checked before anything is queued
+    if (check_precision_range(g, p, "cos_mc_run") != COS_OK)
+        return COS_EINVAL;
     if (value_bytes(p) == 2 && g.path == COS_PATH_FUSED)
         return fail(COS_EINVAL, "cos_mc_run: 16-bit level storage runs on the streamed plan only");
     if (p == COS_FP16_RESCALED && g.h16.empty())

@@ -56,7 +56,8 @@ def _create(g, **over):
 
 
 @pytest.mark.parametrize("case", ["root_width", "final_width", "zero_width", "src_level", "dst_level",
-                                  "nan_a", "neg_b", "inf_k", "neg_epl", "null_src"])
+                                  "nan_a", "neg_b", "inf_k", "neg_epl", "null_src", "c0_overflow",
+                                  "g_overflow"])
 def test_create_rejects_invalid_input(case):
     g, _ = make_config("tiny", S=1)
     g = g.copy()
@@ -81,6 +82,10 @@ def test_create_rejects_invalid_input(case):
         g.epl[1] = -1
     elif case == "null_src":
         over["src"] = None
+    elif case == "c0_overflow":  # finite b and k, but 1 + b|k|^2 is not finite in binary64
+        g.b[4], g.k[4] = 1e300, (1e10, 0.0, 0.0)
+    elif case == "g_overflow":  # 1 + b |k|^2 stays finite, 2 b k overflows
+        g.b[4], g.k[4] = 1e308, (1.0, 0.0, 0.0)
     st, msg, h = _create(g, **over)
     assert st == -1, (st, msg)
     assert msg and not h.value
