@@ -131,6 +131,12 @@ class Graph:
 
         x: float64[R, S] on the device, R = 3 (coordinates) for rational factors or
         n_slots (each sample's table) for lookup factors.
+
+        Stream order: tensors are allocated (and x, out, workspace are usually
+        written) on the current stream.  When `stream` is another stream it first
+        waits for the current one, and every tensor the call uses is marked as in
+        use on `stream`, so the caching allocator cannot hand its memory out again
+        before the evaluation has finished there.
         """
         rows = self.n_inputs
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 2
@@ -147,10 +153,18 @@ class Graph:
         if workspace is None:
             workspace = torch.empty(self.workspace_bytes(S, precision), dtype=torch.uint8, device=x.device)
         # a workspace smaller than workspace_bytes(S) makes the library sweep in sample chunks
-        st = stream if stream is not None else torch.cuda.current_stream(x.device)
+        cur = torch.cuda.current_stream(x.device)
+        st = stream if stream is not None else cur
+        side = st.cuda_stream != cur.cuda_stream
+        if side:
+            st.wait_stream(cur)
         check(LIB.cos_evaluate(self.handle, x.data_ptr(), S, PRECISIONS[precision], out.data_ptr(),
                                out_exp.data_ptr() if out_exp is not None else None, workspace.data_ptr(),
                                workspace.numel() * workspace.element_size(), st.cuda_stream), "cos_evaluate")
+        if side:
+            for t in (x, out, out_exp, workspace):
+                if t is not None:
+                    t.record_stream(st)
         return out
 
     def close(self):

@@ -42,10 +42,20 @@ class Walkers:
         check(LIB.cos_mc_workspace_size(graph.handle, self.C, PRECISIONS[precision], ctypes.byref(nb)),
               "cos_mc_workspace_size")
         self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+        self._adopt(torch.cuda.current_stream(dev))
         with torch.cuda.stream(self.stream):
             graph.evaluate(self.x, precision, out=self.v, stream=self.stream)
         self.step = 0          # global step index of the next step
         self.steps_summed = 0  # steps in the current sums
+
+    def _adopt(self, made_on: torch.cuda.Stream) -> None:
+        """The state tensors were allocated and written on `made_on`; when the walkers run on another
+        stream, that stream waits for those writes and the tensors are marked as in use on it (the
+        caching allocator then keeps their memory until the walkers' own work is done)."""
+        if self.stream.cuda_stream != made_on.cuda_stream:
+            self.stream.wait_stream(made_on)
+            for t in (self.x, self.v, self.accepted, self.acc, self.workspace):
+                t.record_stream(self.stream)
 
     def save(self, path) -> None:
         """Checkpoint the walkers (positions, values, sums, step index, seed, sigma) to a .npz file.
@@ -75,7 +85,7 @@ class Walkers:
               "cos_mc_workspace_size")
         w.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
         w.step, w.steps_summed = int(st["step"]), int(st["steps_summed"])
-        torch.cuda.synchronize(dev)
+        w._adopt(torch.cuda.current_stream(dev))
         return w
 
     def run(self, n_steps: int) -> "Walkers":

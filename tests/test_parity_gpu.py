@@ -354,6 +354,68 @@ def test_side_stream(P):
     assert_parity(y.cpu().numpy(), V, Q, "fp64", "side stream")
 
 
+def test_side_stream_outside_its_context(P):
+    """evaluate(stream=s) while the current stream is another one: s waits for the samples written on the
+    current stream, and the temporary workspace and output stay reserved until s has finished (memory
+    allocated and overwritten on the current stream right after the call must not land in them)."""
+    g, x = make_config("precision", S=2048)
+    G = graph(P, g)
+    V, Q = oracle_ref(g, x)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    say("side stream outside its context: precision fp32r S=2048")
+    for precision in ("fp64", "fp32r"):
+        xd = torch.zeros((3, x.shape[1]), dtype=torch.float64, device="cuda:0")
+        xd.copy_(torch.from_numpy(x).to("cuda:0"))  # written on the current stream
+        y = G.evaluate(xd, precision, stream=s)
+        del xd
+        scribble = [torch.full((G.workspace_bytes(x.shape[1], precision) // 8 + 1,), float("nan"),
+                               dtype=torch.float64, device="cuda:0") for _ in range(2)]
+        s.synchronize()
+        torch.cuda.synchronize()
+        assert_parity(y.cpu().numpy(), V, Q, precision, "side stream, outside its context")
+        del scribble
+
+
+def test_walkers_on_side_stream(P):
+    """Walkers created on the current stream and run on another: the side stream waits for the state the
+    constructor wrote, and the same chain results as on the current stream (bit for bit)."""
+    g, x = make_config("tiny", S=512)
+    G = graph(P, g)
+    ref = P.Walkers(G, to_dev(x), "fp64", seed=3, sigma=0.7).run(20)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    W = P.Walkers(G, to_dev(x), "fp64", seed=3, sigma=0.7, stream=s).run(20)
+    s.synchronize()
+    for a, b in ((W.x, ref.x), (W.v, ref.v), (W.accepted, ref.accepted), (W.acc, ref.acc)):
+        assert torch.equal(a, b)
+
+
+def test_binary32_range_guard(P):
+    """A parameter that is finite in binary64 but rounds to infinity in binary32: FP64 evaluates it (parity
+    with the oracle); every binary32 precision is refused with a message, by cos_evaluate, by the server
+    and by the Monte Carlo walkers."""
+    g, x = make_config("tiny")
+    g = g.copy()
+    g.a[3] = 1e39
+    G = graph(P, g)
+    V, Q = oracle_ref(g, x)
+    assert_parity(gpu_eval(G, x, "fp64"), V, Q, "fp64", "a beyond binary32")
+    xd = to_dev(x)
+    for p in ("fp32r", "fp32", "fp16r", "bf16r"):
+        with pytest.raises(P.CosError, match="binary32 range"):
+            G.evaluate(xd, p)
+    srv = P.Server(1 << 26, 4)
+    try:
+        gid = srv.add_graph(G)
+        with pytest.raises(P.CosError, match="binary32 range"):
+            srv.submit(gid, xd, "fp32r")
+    finally:
+        srv.close()
+    with pytest.raises(P.CosError, match="binary32 range"):
+        P.Walkers(G, xd, "fp32r")
+
+
 def test_timing_probe_counts_launches(P):
     g, x = make_config("mid", S=1024)
     G = graph(P, g)
