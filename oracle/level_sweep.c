@@ -192,9 +192,10 @@ static int sweep(int32_t kind, int32_t L, const int64_t *widths, const int64_t *
     int used = 1;
 
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
-#pragma omp parallel
+    /* the thread count applies to this call only (a num_threads clause, not
+       omp_set_num_threads, which would persist into later calls) */
+    const int nt = nthreads > 0 ? (int)nthreads : omp_get_max_threads();
+#pragma omp parallel num_threads(nt)
 #endif
     {
 #ifdef _OPENMP
