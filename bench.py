@@ -44,7 +44,9 @@ FLOPS_PER_EDGE_SAMPLE = 13
 # 16-bit storage has no fixed tolerance: its bar is a per-sample bound derived from the
 # arithmetic, checked by the parity tests; the bench reports its errors only
 TOL = {"fp64": 1e-12, "fp32r": 1e-5, "fp32": 1e-5, "fp16r": None, "bf16r": None}
+# arithmetic type of the path, and the type the level values are stored in between levels
 DTYPE = {"fp64": "f64", "fp32r": "f32", "fp32": "f32", "fp16r": "f32", "bf16r": "f32"}
+STORAGE = {"fp64": "f64", "fp32r": "f32", "fp32": "f32", "fp16r": "f16", "bf16r": "bf16"}
 VALUE_BYTES = {"fp64": 8, "fp32r": 4, "fp32": 4, "fp16r": 2, "bf16r": 2}
 WORKLOAD_TEXT = {
     "tiny": "tiny: L=4, widths [1,3,4,3,1], in-degree 2, S=1024, x~U[-1,1]^3",
@@ -103,34 +105,54 @@ def cpu_info() -> str:
         return platform.processor()
 
 
-def cpu_baseline_leg(g, x, idx_ref, target_s: float = 12.0):
-    """Time the FP64 oracle on the host cores; also return its values on idx_ref."""
+def _oracle_rate(g, xs, threads, target_s):
+    """Sweep xs with the oracle repeatedly for about target_s seconds: (edge-sample updates/s, threads used,
+    passes, seconds)."""
     import oracle
 
-    S = x.shape[1]
-    E = g.n_edges
-    # calibrate on a small slice, then time a bounded sample of ~target_s seconds
-    cal = min(S, 512)
-    t0 = time.perf_counter()
-    oracle.sweep(g, np.ascontiguousarray(x[:, :cal]))
-    dt = max(time.perf_counter() - t0, 1e-6)
-    n = int(min(S, max(cal, cal * target_s / dt)))
-    xs = np.ascontiguousarray(x[:, :n])
-    # a workload the oracle finishes quickly is swept repeatedly until about target_s seconds have run
-    reps = 0
-    t0 = time.perf_counter()
+    reps, t0 = 0, time.perf_counter()
     while True:
-        _, used = oracle.sweep(g, xs, return_threads=True)
+        _, used = oracle.sweep(g, xs, threads=threads, return_threads=True)
         reps += 1
         t = time.perf_counter() - t0
         if t >= 0.9 * target_s or reps >= 10000:
             break
+    return g.n_edges * xs.shape[1] * reps / t, int(used), reps, t
+
+
+def _oracle_sample(g, x, threads, target_s):
+    """Samples the oracle sweeps in about target_s seconds at the given thread count (calibrated on a small
+    slice), at most all of them."""
+    import oracle
+
+    S = x.shape[1]
+    cal = min(S, 256)
+    t0 = time.perf_counter()
+    oracle.sweep(g, np.ascontiguousarray(x[:, :cal]), threads=threads)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    return int(min(S, max(cal, cal * target_s / dt)))
+
+
+def cpu_baseline_leg(g, x, idx_ref, target_s: float = 12.0):
+    """Time the FP64 oracle on the host cores (every core, then one thread) on a bounded sample of the same
+    workload; also return its values on idx_ref, the reference for the GPU results' error."""
+    import oracle
+
+    S = x.shape[1]
+    E = g.n_edges
+    n = _oracle_sample(g, x, 0, target_s)
+    rate, used, reps, t = _oracle_rate(g, np.ascontiguousarray(x[:, :n]), 0, target_s)
+    n1 = _oracle_sample(g, x, 1, target_s / 3)
+    rate1, _, reps1, t1 = _oracle_rate(g, np.ascontiguousarray(x[:, :n1]), 1, target_s / 3)
     xr = np.ascontiguousarray(x[:, idx_ref])
     V = oracle.sweep(g, xr, "value")
     Q = oracle.sweep(g, xr, "square")
-    base = {"value": E * n * reps / t, "unit": UNIT, "cores": int(used), "kind": "oracle",
+    base = {"value": rate, "unit": UNIT, "cores": used, "kind": "oracle",
             "sample": f"first {n} of {S} samples of the same graph ({E} edges), FP64 level sweep, "
-                      f"{reps} pass(es), {t:.1f} s on {cpu_info()}"}
+                      f"{reps} pass(es), {t:.1f} s on {cpu_info()}",
+            "single_thread": {"value": rate1, "unit": UNIT, "cores": 1,
+                              "sample": f"first {n1} of {S} samples, {reps1} pass(es), {t1:.1f} s"},
+            "parallel_speedup": rate / rate1}
     return base, V, Q
 
 
@@ -178,8 +200,9 @@ def run_timed(P, G, xd, precision, steps, warmup):
     return ms, kern, out
 
 
-def roofline(g, S_pad, precision, kern, steps, workload):
-    """Roofline of the dominant kernel class, from its live HIP-event timings."""
+def roofline(g, S_pad, precision, kern, steps, workload, copy_gbs=None):
+    """Roofline of the dominant kernel class, from its live HIP-event timings.  copy_gbs: the bandwidth a plain
+    device copy reaches on this GPU, reported beside the nominal peak for HBM-bound kernels."""
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     if dom == "level":
         per_launch = level_bytes(g, S_pad, precision)
@@ -218,6 +241,9 @@ def roofline(g, S_pad, precision, kern, steps, workload):
             r["other_term"]["table_gbs_read"] = es_step / n_launch * table_entry_bytes(g, precision) / t_launch / 1e9
     else:
         r = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "kernel": dom}
+    if r.get("bound") == "hbm" and copy_gbs:
+        r["copy_GBps"] = copy_gbs
+        r["frac_of_copy"] = r["achieved"] / copy_gbs
     r["traffic"] = profiled_traffic(r.get("kernel"), workload, precision)
     r["kernel_src_id"] = kernel_source_id(r.get("kernel"))
     return r
@@ -263,7 +289,7 @@ def profiled_traffic(kernel, workload, precision):
     return None
 
 
-def calibrate_copy(steps: int, nbytes: int = 1 << 30):
+def calibrate_copy(steps: int, nbytes: int = 1 << 30) -> dict:
     """A plain device-to-device copy of nbytes: reads nbytes and writes nbytes per launch."""
     import torch
 
@@ -279,9 +305,10 @@ def calibrate_copy(steps: int, nbytes: int = 1 << 30):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
-    print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": nbytes,
-                      "bytes_written_per_launch": nbytes, "ms_per_launch": ms,
-                      "copy_GBps": 2 * nbytes / (ms / 1000) / 1e9}), flush=True)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"calibration": "device copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+            "ms_per_launch": ms, "copy_GBps": 2 * nbytes / (ms / 1000) / 1e9}
 
 
 FACTOR_TEXT = {"rational": "; w_e = a_e/(1+b_e|x-k_e|^2), x in R^3 per sample",
@@ -318,7 +345,7 @@ MC_TEXT = ("Metropolis walkers for |V| (one per sample of the workload), uniform
            "{sigma}, Philox4x64-10 on the device; a step = propose + level sweep + accept")
 
 
-def mc_leg(P, args, eval_ms):
+def mc_leg(P, args, workload, eval_ms):
     """Monte Carlo walkers on the workload's graph: one walker per sample, steps/s and edge-sample updates/s
     including proposal and acceptance, against a plain evaluation of the same samples (eval_ms).  The oracle
     re-runs the first walkers' chains in the CPU-baseline leg."""
@@ -326,10 +353,10 @@ def mc_leg(P, args, eval_ms):
 
     from workloads import make_config
 
-    g, x = make_config(args.workload)
+    g, x = make_config(workload)
     C, sigma, seed = x.shape[1], 0.5, 1
     G = P.Graph.from_leveled(g)
-    res = {"workload": WORKLOAD_TEXT[args.workload] + "; " + MC_TEXT.format(sigma=sigma), "walkers": C}
+    res = {"workload": WORKLOAD_TEXT[workload] + "; " + MC_TEXT.format(sigma=sigma), "walkers": C}
     n_check = min(C, 64)
     check_steps = 8
     for p in ("fp64", "fp32r"):
@@ -514,16 +541,24 @@ def serving_leg(P, args):
     res["burst"] = {p: batched(p, zeros) for p in ("fp64", "fp32r", "fp16r", "bf16r")}
     res["burst"]["fp64_single"] = single(zeros)
     cap_rps = len(reqs) / (res["burst"]["fp64"]["makespan_ms"] / 1e3)
-    rng = np.random.default_rng(4)
-    gaps = rng.exponential(1.0, len(reqs))
     res["poisson"] = {}
+    modes = {"fp64_batched": lambda a: batched("fp64", a), "fp32r_batched": lambda a: batched("fp32r", a),
+             "fp64_single": single}
     for load in args.serve_loads:
         rate = load * cap_rps
-        arr = np.cumsum(gaps) / rate * 1e9
-        arr -= arr[0]
-        print(f"# serving poisson load {load}: {rate:.0f} requests/s", file=sys.stderr, flush=True)
-        res["poisson"][str(load)] = {"rate_rps": rate, "fp64_batched": batched("fp64", arr),
-                                     "fp32r_batched": batched("fp32r", arr), "fp64_single": single(arr)}
+        runs = {}
+        for seed in args.serve_seeds:
+            gaps = np.random.default_rng(seed).exponential(1.0, len(reqs))
+            arr = np.cumsum(gaps) / rate * 1e9
+            arr -= arr[0]
+            print(f"# serving poisson load {load} seed {seed}: {rate:.0f} requests/s", file=sys.stderr, flush=True)
+            runs[str(seed)] = {m: f(arr) for m, f in modes.items()}
+        summary = {}
+        for m in modes:
+            for q in ("p50_ms", "p99_ms"):
+                v = [runs[k][m][q] for k in runs]
+                summary[f"{m}_{q}"] = {"median": _pct(v, 50), "min": float(min(v)), "max": float(max(v))}
+        res["poisson"][str(load)] = {"rate_rps": rate, "seeds": runs, "across_seeds": summary}
     torch.cuda.synchronize()
     # results of the last trace: batched FP64 bit-identical to one-at-a-time FP64 for every request
     same = torch.eq(outs["fp64"].view(torch.int64), outs["single"].view(torch.int64))
@@ -540,19 +575,76 @@ def serving_leg(P, args):
     return res, checks
 
 
+def sampled_idx(S, n, seed):
+    """Samples 0 and S-1 plus a seeded draw, n in all (at most S)."""
+    return np.unique(np.concatenate([[0, S - 1], np.random.default_rng(seed).choice(S, min(S, n) - 2,
+                                                                                    replace=False)]))
+
+
+def extra_leg(P, name, precisions, args, copy_gbs):
+    """Another workload timed at each precision (roofline, sampled outputs for the CPU-baseline leg's check,
+    and the FP32-rescaled result against the GPU's own FP64 result on every sample)."""
+    import torch
+
+    from workloads import make_config
+
+    g, x = make_config(name)
+    S = x.shape[1]
+    S_pad = (S + 255) // 256 * 256
+    G = P.Graph.from_leveled(g)
+    xd = torch.from_numpy(x).to("cuda:0")
+    idx = sampled_idx(S, 1024, 0)
+    res = {"workload": WORKLOAD_TEXT[name] + FACTOR_TEXT["rational"], "L": g.L, "edges": g.n_edges, "S": S}
+    check = {"graph": g, "x": np.ascontiguousarray(x[:, idx]), "y": {}, "into": res, "full_x": x, "name": name}
+    full = {}
+    for p in precisions:
+        print(f"# {name} {p}", file=sys.stderr, flush=True)
+        ms, kern, out = run_timed(P, G, xd, p, args.steps, args.warmup)
+        res[p] = {"value": g.n_edges * S / (ms / 1000.0), "ms_per_step": ms, "dtype": DTYPE[p],
+                  "storage_dtype": STORAGE[p], "kernels": kern,
+                  "roofline": roofline(g, S_pad, p, kern, args.steps, name, copy_gbs)}
+        y = out.cpu().numpy()
+        full[p] = y
+        check["y"][p] = y[idx]
+    if "fp64" in full:
+        for p in [q for q in full if q != "fp64"]:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                rel = np.abs(full[p] - full["fp64"]) / np.abs(full["fp64"])
+            rel = rel[np.isfinite(rel)]
+            res[p]["vs_gpu_fp64_plain_rel"] = {"p50": float(np.percentile(rel, 50)),
+                                               "p99": float(np.percentile(rel, 99)), "max": float(rel.max()),
+                                               "samples": int(len(rel))}
+    G.close()
+    return res, [check]
+
+
+def oracle_full_pass(g, x):
+    """One oracle pass over every sample of a workload on all host cores (edge-sample updates/s)."""
+    import oracle
+
+    t0 = time.perf_counter()
+    _, used = oracle.sweep(g, np.ascontiguousarray(x), return_threads=True)
+    t = time.perf_counter() - t0
+    return {"value": g.n_edges * x.shape[1] / t, "unit": UNIT, "cores": int(used), "samples": int(x.shape[1]),
+            "seconds": t}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mid", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--precision", default="fp64", choices=sorted(TOL))
-    ap.add_argument("--variants", default="fp32r,fp16r,bf16r",
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--precision", default="fp32r", choices=sorted(TOL))
+    ap.add_argument("--variants", default="fp64,fp16r,bf16r",
                     help="comma list of extra precisions to time ('' for none; fp16r is skipped for lookup factors)")
+    ap.add_argument("--extra", default="mid,precision",
+                    help="comma list of other workloads timed at FP64 and FP32-rescaled ('' for none)")
+    ap.add_argument("--mc-workload", default="mid", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="time a plain 1 GiB device copy (reference for HBM counters and bandwidth)")
+                    help="only time a plain 1 GiB device copy (reference for HBM counters and bandwidth)")
     ap.add_argument("--factor", default="rational", choices=["rational", "lookup"],
                     help="edge-factor kind of the timed workload")
     ap.add_argument("--no-lookup", action="store_true", help="skip the lookup-factor block of the default run")
@@ -562,16 +654,18 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=float, default=24.0)
     ap.add_argument("--serve-loads", type=lambda v: [float(t) for t in v.split(",") if t], default=[0.5, 0.9])
+    ap.add_argument("--serve-seeds", type=lambda v: [int(t) for t in v.split(",") if t], default=[4, 14, 24],
+                    help="seeds of the Poisson arrival traces replayed at each load")
     args = ap.parse_args()
-    if args.calibrate_copy:
-        calibrate_copy(args.steps)
-        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: samples are independent, so the path "
                                    "would replicate the graph on every GPU and give each S/N samples with no "
                                    "per-level exchange, but no multi-GPU run is provided",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.calibrate_copy:
+        print(json.dumps(calibrate_copy(args.steps)), flush=True)
+        return
 
     import torch
 
@@ -584,6 +678,8 @@ def main():
             reference_checks(checks)
         print(json.dumps({"serving": res}), flush=True)
         return
+    copy = calibrate_copy(10)
+    copy_gbs = copy["copy_GBps"]
     g, x = make_config(args.workload, factor=args.factor)
     S = x.shape[1]
     E = g.n_edges
@@ -602,21 +698,35 @@ def main():
         "dtype": DTYPE[args.precision], "data": "synthetic (seeded generator; stands in for the paper's CoS graphs)",
         "config": {"workload": WORKLOAD_TEXT[args.workload] + FACTOR_TEXT[args.factor].format(n=g.n_inputs),
                    "L": g.L, "edges": E, "nodes": g.n_nodes, "S": S, "precision": args.precision,
-                   "factor": args.factor, "seed": g.meta.get("seed")},
+                   "storage_dtype": STORAGE[args.precision], "factor": args.factor, "seed": g.meta.get("seed")},
         "kernels": kern,
-        "roofline": roofline(g, S_pad, args.precision, kern, args.steps, args.workload),
+        "roofline": roofline(g, S_pad, args.precision, kern, args.steps, args.workload, copy_gbs),
+        "copy_calibration": copy,
     }
     variants = {}
     for pv in [v for v in args.variants.split(",") if v and v != args.precision
                and not (v == "fp16r" and g.kind == "lookup")]:
         print(f"# variant {pv}", file=sys.stderr, flush=True)
         msv, kv, outv = run_timed(P, G, xd, pv, args.steps, args.warmup)
-        variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "kernels": kv,
-                        "roofline": roofline(g, S_pad, pv, kv, args.steps, args.workload), "_y": outv.cpu().numpy()}
+        variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "dtype": DTYPE[pv],
+                        "storage_dtype": STORAGE[pv], "kernels": kv,
+                        "roofline": roofline(g, S_pad, pv, kv, args.steps, args.workload, copy_gbs),
+                        "_y": outv.cpu().numpy()}
+    if "fp64" in variants:
+        variants["fp64"]["speed_ratio_headline_over_fp64"] = value / variants["fp64"]["value"]
+    G.close()
     checks = []
+    extras = {}
+    for name in [w for w in args.extra.split(",") if w and w != args.workload]:
+        extras[name], c = extra_leg(P, name, ["fp64", "fp32r"], args, copy_gbs)
+        checks += c
     if args.factor == "rational" and not args.no_mc:
-        eval_ms = {args.precision: ms, **{k: v["ms_per_step"] for k, v in variants.items()}}
-        result["mc"], c = mc_leg(P, args, eval_ms)
+        eval_ms = {}
+        if args.mc_workload == args.workload:
+            eval_ms = {args.precision: ms, **{k: v["ms_per_step"] for k, v in variants.items()}}
+        elif args.mc_workload in extras:
+            eval_ms = {p: extras[args.mc_workload][p]["ms_per_step"] for p in ("fp64", "fp32r")}
+        result["mc"], c = mc_leg(P, args, args.mc_workload, eval_ms)
         checks += c
     if args.factor == "rational" and not args.no_lookup:
         result["lookup"], c = lookup_leg(P, args)
@@ -626,13 +736,17 @@ def main():
         checks += c
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        idx = np.unique(np.concatenate([[0, S - 1], np.random.default_rng(0).choice(S, min(S, 1024) - 2,
-                                                                                     replace=False)]))
+        idx = sampled_idx(S, 1024, 0)
         base, V, Q = cpu_baseline_leg(g, x, idx, args.cpu_seconds)
         result["cpu_baseline"] = base
         result["accuracy"] = error_stats(y[idx], V, Q, args.precision)
         for pv, d in variants.items():
             d["accuracy"] = error_stats(d["_y"][idx], V, Q, pv)
+        # the oracle over every sample of each workload, one pass on all cores
+        result["oracle_full_S"] = {args.workload: oracle_full_pass(g, x)}
+        for c in checks:
+            if "full_x" in c:
+                result["oracle_full_S"][c["name"]] = oracle_full_pass(c["graph"], c.pop("full_x"))
         reference_checks(checks)
     else:
         result["cpu_baseline"] = None
@@ -641,6 +755,7 @@ def main():
     for d in variants.values():
         d.pop("_y", None)
     result["variants"] = variants
+    result["extra_workloads"] = extras
     print(json.dumps(result), flush=True)
 
 
