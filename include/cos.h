@@ -427,7 +427,8 @@ cos_status cos_server_destroy(cos_server *srv);
  * device time in milliseconds and the launch count for kernel class `kind`,
  * and clears that class's records.  Kinds: 0 interior level gather,
  * 1 fused multi-level (LDS-resident), 2 final-node partial sums,
- * 3 final-node combine, 4 scratch fills, 5 serving step.
+ * 3 final-node combine, 4 scratch fills, 5 serving step, 6 chunk sums of
+ * interior nodes of high in-degree.
  * Errors: COS_EINVAL (bad kind), COS_EDEVICE.
  */
 cos_status cos_timing_enable(int32_t enable);

@@ -22,7 +22,7 @@ COS_OK, COS_EINVAL, COS_ENOMEM, COS_EDEVICE, COS_EAGAIN, COS_ECANCELED = 0, -1, 
 STATUS_NAMES = {0: "COS_OK", -1: "COS_EINVAL", -2: "COS_ENOMEM", -3: "COS_EDEVICE", -4: "COS_EAGAIN",
                 -5: "COS_ECANCELED"}
 PRECISIONS = {"fp64": 0, "fp32r": 1, "fp32": 2, "fp16r": 3, "bf16r": 4}
-KINDS = {"level": 0, "fused": 1, "final_partial": 2, "final_combine": 3, "fill": 4, "serve": 5}
+KINDS = {"level": 0, "fused": 1, "final_partial": 2, "final_combine": 3, "fill": 4, "serve": 5, "hub": 6}
 
 # every symbol include/cos.h declares (checked by the tests)
 EXPORTS = [

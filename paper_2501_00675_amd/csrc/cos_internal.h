@@ -72,6 +72,12 @@ struct LevelDesc {
     int64_t n_edges;
     int64_t rp_begin;  // offset of this level's row_ptr[w_dst + 1] in the row_ptr array
     int64_t max_deg;   // largest in-degree in this level
+    // rows of more than kHubEdges in-edges (interior levels): their chunks of
+    // kFinalChunk edges are entries [hub_begin, hub_begin + n_hub_chunks) of
+    // Graph::d_hub_chunks, row by row; the first record of such a row holds,
+    // in zero_rows, the index of its first chunk relative to hub_begin
+    int64_t hub_begin = 0;
+    int64_t n_hub_chunks = 0;
 };
 
 // Compact level table read by the fused kernel (device copy).
@@ -113,6 +119,8 @@ struct Graph {
     EdgeRecL *d_edgesL = nullptr;     // lookup records (every level, every precision)
     LevelDev *d_levels = nullptr;     // L entries
     int32_t *d_h16 = nullptr;         // h16 on the device (L entries; NULL when h16 is empty)
+    int32_t *d_hub_chunks = nullptr;  // (first edge, end edge) pairs of the chunks of high in-degree rows
+    int64_t max_hub_chunks = 0;       // most chunks of such rows in one level
     int device = 0;
     cos_path path = COS_PATH_AUTO;    // kernel plan chosen by cos_graph_set_path
 };
@@ -130,7 +138,7 @@ cos_status hip_fail(hipError_t err, const char *what);
 
 // ---------------------------------------------------------------- timing probe
 enum KernelKind { KK_LEVEL = 0, KK_FUSED = 1, KK_FINAL_PARTIAL = 2, KK_FINAL_COMBINE = 3,
-                  KK_FILL = 4, KK_SERVE = 5, KK_COUNT = 6 };
+                  KK_FILL = 4, KK_SERVE = 5, KK_HUB = 6, KK_COUNT = 7 };
 bool timing_on();
 void timing_begin(int kind, hipStream_t s);
 void timing_end(int kind, hipStream_t s);
@@ -150,6 +158,9 @@ constexpr int kSamplePad = 256;      // S is padded to a multiple of this
 constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
 constexpr int kFinalChunk = 256;     // final-node edges per partial sum (4 quarters of 64)
 constexpr int kQuarter = kFinalChunk / 4;
+// An interior node with more in-edges than this is summed in chunks of
+// kFinalChunk edges (the final node's order) instead of edge after edge.
+constexpr int kHubEdges = 1024;
 constexpr int kFusedWaves = 16;      // wavefronts per workgroup of the LDS-resident sweep
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -173,6 +184,7 @@ struct Workspace {
     size_t bytes = 0;
     size_t off_buf0 = 0, off_buf1 = 0, off_maxbits = 0, off_partial = 0;
     size_t off_table32 = 0;    // binary32 sample tables [n_slots][S_pad] (lookup, binary32 paths), if used
+    size_t off_hub = 0;        // chunk sums of high in-degree rows [chunk][S_pad] in the value type, if any
     bool table32 = false;
     int64_t S_chunk = 0;       // samples per sweep
     int64_t S_pad = 0;         // row length of the level buffers
@@ -199,9 +211,13 @@ int64_t max_chunk(const Graph &g, cos_precision p);
 // h_next the headroom exponent folded into cur_max (0 unless binary16).
 // t32 (nullable): binary32 sample tables [n_slots][ld] of a lookup graph,
 // read instead of x by the interior levels.
+// hub (nullable): room for the level's chunk sums of high in-degree rows,
+// computed by a launch of their own before the level's; NULL: the level
+// kernel sums such rows itself (the same bits).
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur,
                         int64_t ld, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
-                        uint32_t *cur_max, int32_t h_next, hipStream_t s, const float *t32 = nullptr);
+                        uint32_t *cur_max, int32_t h_next, hipStream_t s, const float *t32 = nullptr,
+                        void *hub = nullptr);
 // t32[i][s] = fl32(x[i][s]) for s < S, 0 for S <= s < ld (n rows).
 hipError_t launch_table32(const double *x, int64_t xs, int64_t S, int32_t n, float *t32, int64_t ld,
                           hipStream_t s);

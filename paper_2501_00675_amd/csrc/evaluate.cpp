@@ -37,6 +37,8 @@ Workspace layout_for_chunk(const Graph &g, int64_t S_chunk, cos_precision p, boo
     w.table32 = with_table32 && uses_table32(g, p);
     if (w.table32)
         w.off_table32 = take(static_cast<size_t>(g.n_slots) * w.S_pad * sizeof(float));
+    if (g.max_hub_chunks > 0)  // chunk sums of rows of high in-degree, binary64 or binary32
+        w.off_hub = take(static_cast<size_t>(g.max_hub_chunks) * w.S_pad * (p == COS_FP64 ? 8 : 4));
     w.bytes = std::max<size_t>(off, 256);
     return w;
 }
@@ -95,7 +97,8 @@ hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char
         const uint32_t *pm = maxbits ? maxbits + static_cast<int64_t>(l - 1) * w.S_pad : nullptr;
         uint32_t *cm = (maxbits && l <= g.L - 2) ? maxbits + static_cast<int64_t>(l) * w.S_pad : nullptr;
         const int32_t h_next = l <= g.L - 2 ? headroom(g, p, l + 1) : 0;
-        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st, t32);
+        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st, t32,
+                           g.max_hub_chunks > 0 ? base + w.off_hub : nullptr);
         prev = cur;
     }
     if (err == hipSuccess)

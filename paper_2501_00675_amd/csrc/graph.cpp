@@ -334,6 +334,7 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     std::vector<EdgeRec32> recs32(lookup ? 0 : n_edges + kEdgePad, EdgeRec32{});
     std::vector<EdgeRecL> recsL(lookup ? n_edges + kEdgePad : 0, EdgeRecL{});
     std::vector<LevelDev> ldev(L);
+    std::vector<int32_t> hub_chunks;  // (first edge, end edge) pairs
     for (int32_t l = 1; l <= L; ++l) {
         LevelDesc &d = G.levels[l - 1];
         int32_t *r = row_ptr.data() + d.rp_begin;
@@ -402,6 +403,29 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
                 recs32[last].zero_rows = zr;
             }
         }
+        // rows of high in-degree (interior levels): their chunk lists, and the
+        // index of each such row's first chunk in the row's first record
+        if (l < L) {
+            d.hub_begin = static_cast<int64_t>(hub_chunks.size() / 2);
+            for (int64_t j = 0; j < d.w_dst; ++j) {
+                const int64_t e_lo = r[j], e_hi = r[j + 1];
+                if (e_hi - e_lo <= kHubEdges)
+                    continue;
+                const int32_t first = static_cast<int32_t>(hub_chunks.size() / 2 - d.hub_begin);
+                if (lookup)
+                    recsL[e_lo].zero_rows = first;
+                else {
+                    recs[e_lo].zero_rows = first;
+                    recs32[e_lo].zero_rows = first;
+                }
+                for (int64_t c = e_lo; c < e_hi; c += kFinalChunk) {
+                    hub_chunks.push_back(static_cast<int32_t>(c));
+                    hub_chunks.push_back(static_cast<int32_t>(std::min<int64_t>(c + kFinalChunk, e_hi)));
+                }
+            }
+            d.n_hub_chunks = static_cast<int64_t>(hub_chunks.size() / 2) - d.hub_begin;
+            G.max_hub_chunks = std::max(G.max_hub_chunks, d.n_hub_chunks);
+        }
         ldev[l - 1] = LevelDev{static_cast<int32_t>(d.w_dst), static_cast<int32_t>(d.rp_begin),
                                static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges)};
     }
@@ -415,7 +439,8 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     const size_t off_recL = off_rec32 + round_up(recs32.size() * sizeof(EdgeRec32), 256);
     const size_t off_lev = off_recL + round_up(recsL.size() * sizeof(EdgeRecL), 256);
     const size_t off_h16 = off_lev + round_up(L * sizeof(LevelDev), 256);
-    const size_t total = off_h16 + round_up(G.h16.size() * sizeof(int32_t), 256);
+    const size_t off_hub = off_h16 + round_up(G.h16.size() * sizeof(int32_t), 256);
+    const size_t total = off_hub + round_up(hub_chunks.size() * sizeof(int32_t), 256);
     hipError_t err = hipGetDevice(&G.device);
     if (err != hipSuccess)
         return hip_fail(err, "hipGetDevice");
@@ -430,6 +455,7 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     G.d_edgesL = lookup ? reinterpret_cast<EdgeRecL *>(base + off_recL) : nullptr;
     G.d_levels = reinterpret_cast<LevelDev *>(base + off_lev);
     G.d_h16 = G.h16.empty() ? nullptr : reinterpret_cast<int32_t *>(base + off_h16);
+    G.d_hub_chunks = hub_chunks.empty() ? nullptr : reinterpret_cast<int32_t *>(base + off_hub);
     err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
     if (err == hipSuccess && !recs.empty())
         err = hipMemcpy(G.d_edges, recs.data(), recs.size() * sizeof(EdgeRec), hipMemcpyHostToDevice);
@@ -441,6 +467,9 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
         err = hipMemcpy(G.d_levels, ldev.data(), L * sizeof(LevelDev), hipMemcpyHostToDevice);
     if (err == hipSuccess && G.d_h16)
         err = hipMemcpy(G.d_h16, G.h16.data(), G.h16.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (err == hipSuccess && G.d_hub_chunks)
+        err = hipMemcpy(G.d_hub_chunks, hub_chunks.data(), hub_chunks.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice);
     if (err != hipSuccess) {
         (void)hipFree(G.d_base);
         return hip_fail(err, "hipMemcpy(graph)");

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
     const int32_t *__restrict__ row_ptr, const typename SweepPath<T, KIND>::Rec *__restrict__ edges, int32_t w_dst, int32_t n_rg,
     int32_t n_tiles, int32_t xcd_group, int32_t reverse_tiles, const V *__restrict__ prev, V *__restrict__ cur, int64_t ld,
     const SampleElem<KIND> *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
-    uint32_t *__restrict__ cur_max, int32_t h_next) {
+    uint32_t *__restrict__ cur_max, int32_t h_next, const T *__restrict__ hub_partial) {
     int tile, rg;
     if (!block_tile(n_rg, n_tiles, xcd_group, reverse_tiles, tile, rg))
         return;
@@ -87,10 +87,11 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
         esh[m] = (RESCALE && prev_max) ? ilogb_bits(prev_max[tbase + lane + kWave * m]) : 0;
         lmax[m] = 0u;
     }
+    static_assert(ROWS == kWaveRows, "level_wave_rows takes kWaveRows rows per wave");
     const int jbeg = min(rg * (4 * ROWS) + wave * ROWS, w_dst);
     const int jend = min(jbeg + ROWS, w_dst);
     level_wave_rows<T, K, FROM_ROOT, RESCALE, KIND, V>(row_ptr, edges, jbeg, jend, prev, cur, ld, tbase, lane, smp,
-                                                       esh, lmax);
+                                                       esh, lmax, hub_partial);
     if constexpr (RESCALE) {
         if (cur_max) {
             if (h_next)  // exact: |value| <= 2^15 and h_next <= 96
@@ -101,6 +102,49 @@ __global__ __launch_bounds__(kBlock) void level_gather_kernel(
             fold_max<K, 4>(red, lmax, wave, lane, cur_max + tbase);
         }
     }
+}
+
+// Interior rows of high in-degree: block (sample tile, chunk c) sums chunk c
+// of the level's list (kFinalChunk edges of one such row; chunks[2c],
+// chunks[2c+1] its first and end edge) in the value type T, wave w the w-th
+// quarter, and writes ((q0 + q1) + q2) + q3 to partial[c][s] -- hub_sum's
+// chunk sums, which the level kernel then adds in ascending order.
+template <typename T, int K, bool FROM_ROOT, int KIND, typename V>
+__global__ __launch_bounds__(kBlock) void hub_partial_kernel(
+    const int32_t *__restrict__ chunks, int32_t n_chunks, const typename SweepPath<T, KIND>::Rec *__restrict__ edges,
+    const V *__restrict__ prev, int64_t ld, const SampleElem<KIND> *__restrict__ x, int64_t S, int64_t xs,
+    T *__restrict__ partial) {
+    using Rec = typename SweepPath<T, KIND>::Rec;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x / n_chunks;
+    const int c = blockIdx.x - tile * n_chunks;
+    const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
+    typename SweepPath<T, KIND>::template Samples<K> smp;
+    smp.load(x, S, xs, tbase, lane);
+    const ConstPtr<int32_t> ch = as_const(chunks);
+    const int c_lo = ch[2 * c], c_hi = ch[2 * c + 1];
+    const int e_lo = min(c_lo + wave * kQuarter, c_hi);
+    const int e_hi = min(e_lo + kQuarter, c_hi);
+    const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
+    const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(V));
+    const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(V));
+    T acc[K];
+    edge_sum<T, K, true>(edges, e_lo, e_hi, smp, [&](const Rec &r, int m) -> T {
+        if constexpr (FROM_ROOT) {
+            return T(1);
+        } else {
+            const char *row = src_tile + static_cast<uint32_t>(r.src) * row_bytes + lane_off;
+            return static_cast<T>(*reinterpret_cast<const V *>(row + m * kWave * sizeof(V)));
+        }
+    }, acc);
+    __shared__ T red[4][kWave * K];
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        red[wave][lane + kWave * m] = acc[m];
+    __syncthreads();
+    for (int i = threadIdx.x; i < kWave * K; i += kBlock)
+        partial[static_cast<int64_t>(c) * ld + tbase + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
 // Final node, pass 1: block (sample tile, chunk c) sums the edges of chunk c
@@ -170,7 +214,7 @@ int level_k(int64_t w_src) {
 template <typename T, int K, bool RESCALE, int KIND, typename V>
 hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x_,
                           int64_t S, int64_t xs_, const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next,
-                          hipStream_t s, const float *t32) {
+                          hipStream_t s, const float *t32, void *hub) {
     const SampleElem<KIND> *x;
     int64_t xs;
     if constexpr (KIND == FK_LOOKUP_T32) {
@@ -199,17 +243,39 @@ hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, in
         recs = g.d_edges;
     else
         recs = g.d_edges32;
+    // chunk sums of the level's rows of high in-degree, when there is room for them
+    T *hub_partial = nullptr;
+    if (d.n_hub_chunks > 0 && hub) {
+        hub_partial = static_cast<T *>(hub);
+        const int64_t hgrid = n_tiles * d.n_hub_chunks;
+        if (hgrid > INT32_MAX)
+            return hipErrorInvalidConfiguration;
+        const int32_t *chunks = g.d_hub_chunks + 2 * d.hub_begin;
+        const int32_t nc = static_cast<int32_t>(d.n_hub_chunks);
+        TimedLaunch th(KK_HUB, s);
+        if (prev == nullptr)
+            hipLaunchKernelGGL((hub_partial_kernel<T, K, true, KIND, V>), dim3(static_cast<unsigned>(hgrid)),
+                               dim3(kBlock), 0, s, chunks, nc, recs, static_cast<const V *>(nullptr), ld, x, S, xs,
+                               hub_partial);
+        else
+            hipLaunchKernelGGL((hub_partial_kernel<T, K, false, KIND, V>), dim3(static_cast<unsigned>(hgrid)),
+                               dim3(kBlock), 0, s, chunks, nc, recs, static_cast<const V *>(prev), ld, x, S, xs,
+                               hub_partial);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess)
+            return err;
+    }
     TimedLaunch tl(KK_LEVEL, s);
     if (prev == nullptr)
         hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, true, RESCALE, KIND, V>), dim3(grid), dim3(kBlock), 0, s,
                            rp, recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
                            static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, nullptr, static_cast<V *>(cur), ld,
-                           x, S, xs, prev_max, cur_max, h_next);
+                           x, S, xs, prev_max, cur_max, h_next, hub_partial);
     else
         hipLaunchKernelGGL((level_gather_kernel<T, K, kRows, false, RESCALE, KIND, V>), dim3(grid), dim3(kBlock), 0, s,
                            rp, recs, static_cast<int32_t>(d.w_dst), static_cast<int32_t>(n_rg),
                            static_cast<int32_t>(n_tiles), xcd_group, reverse_tiles, static_cast<const V *>(prev),
-                           static_cast<V *>(cur), ld, x, S, xs, prev_max, cur_max, h_next);
+                           static_cast<V *>(cur), ld, x, S, xs, prev_max, cur_max, h_next, hub_partial);
     return hipGetLastError();
 }
 
@@ -218,7 +284,7 @@ hipError_t launch_level_k(const Graph &g, int l, const void *prev, void *cur, in
 template <typename T, bool RESCALE, typename V = T, bool LOOKUP_OK = true>
 hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, int64_t ld, const double *x,
                           int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next,
-                          hipStream_t s, const float *t32) {
+                          hipStream_t s, const float *t32, void *hub) {
     const bool k2 = level_k<T, V>(g.levels[l - 1].w_src) == 2;
     if (g.kind == FK_LOOKUP) {
         if constexpr (!LOOKUP_OK) {
@@ -226,20 +292,20 @@ hipError_t launch_level_t(const Graph &g, int l, const void *prev, void *cur, in
         } else if constexpr (sizeof(T) == sizeof(float)) {
             if (t32)
                 return k2 ? launch_level_k<T, 2, RESCALE, FK_LOOKUP_T32, V>(g, l, prev, cur, ld, x, S, xs, prev_max,
-                                                                            cur_max, h_next, s, t32)
+                                                                            cur_max, h_next, s, t32, hub)
                           : launch_level_k<T, 4, RESCALE, FK_LOOKUP_T32, V>(g, l, prev, cur, ld, x, S, xs, prev_max,
-                                                                            cur_max, h_next, s, t32);
+                                                                            cur_max, h_next, s, t32, hub);
         }
         if constexpr (LOOKUP_OK)
             return k2 ? launch_level_k<T, 2, RESCALE, FK_LOOKUP, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                                    h_next, s, t32)
+                                                                    h_next, s, t32, hub)
                       : launch_level_k<T, 4, RESCALE, FK_LOOKUP, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                                    h_next, s, t32);
+                                                                    h_next, s, t32, hub);
     }
     return k2 ? launch_level_k<T, 2, RESCALE, FK_RATIONAL, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                              h_next, s, t32)
+                                                              h_next, s, t32, hub)
               : launch_level_k<T, 4, RESCALE, FK_RATIONAL, V>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max,
-                                                              h_next, s, t32);
+                                                              h_next, s, t32, hub);
 }
 
 }  // namespace
@@ -250,19 +316,19 @@ int32_t final_chunk_count(int64_t final_in_degree) {
 
 hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
                         const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
-                        int32_t h_next, hipStream_t s, const float *t32) {
+                        int32_t h_next, hipStream_t s, const float *t32, void *hub) {
     switch (p) {
     case COS_FP64:
-        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s, nullptr);
+        return launch_level_t<double, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s, nullptr, hub);
     case COS_FP32_RESCALED:
-        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s, t32);
+        return launch_level_t<float, true>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s, t32, hub);
     case COS_FP32:
-        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s, t32);
+        return launch_level_t<float, false>(g, l, prev, cur, ld, x, S, xs, nullptr, nullptr, 0, s, t32, hub);
     case COS_FP16_RESCALED:
         return launch_level_t<float, true, _Float16, false>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, h_next,
-                                                            s, nullptr);
+                                                            s, nullptr, hub);
     case COS_BF16_RESCALED:
-        return launch_level_t<float, true, __bf16>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s, t32);
+        return launch_level_t<float, true, __bf16>(g, l, prev, cur, ld, x, S, xs, prev_max, cur_max, 0, s, t32, hub);
     }
     return hipErrorInvalidValue;
 }

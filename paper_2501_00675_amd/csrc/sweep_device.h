@@ -208,12 +208,96 @@ using FinalPath = SweepPath<double, KIND == FK_LOOKUP_T32 ? FK_LOOKUP : KIND>;
 template <int KIND>
 using SampleElem = std::conditional_t<KIND == FK_LOOKUP_T32, float, double>;
 
-// One wave computes destination rows [jbeg, jend) of a level for the tile at
-// tbase (64*K samples).  The rows' edges form one contiguous stream, walked in
-// chunks of four: the four records are fetched together (one scalar wait), the
-// 4*K source values requested together (one vector wait), then the factors
-// accumulated.  A row is stored when its flagged last edge has been added;
-// rows without in-edges are stored as zeros.
+// Sum over edges [e_lo, e_hi) of w_e v[src_e] in the type T, sequentially in
+// canonical order from T(0): one quarter of a final-node chunk (binary64) or
+// of a chunk of an interior node of high in-degree.  The source value of edge
+// e comes from src_value(rec, m) (level buffer or LDS).  Full chunks
+// accumulate unconditionally, a tail its first n edges only.
+template <typename T, int K, bool TOGETHER, typename Rec, typename Smp, typename SrcValue>
+__device__ __forceinline__ void edge_sum(const Rec *__restrict__ edges, int e_lo, int e_hi, const Smp &xs,
+                                         SrcValue src_value, T (&acc)[K]) {
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        acc[m] = T(0);
+    auto chunk = [&](auto full, int e, int n) {
+        Rec r[kChunk];
+        load_chunk<kChunk, TOGETHER>(edges + e, r);
+        T v[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                v[u][m] = src_value(r[u], m);
+        T w[kChunk][K];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                w[u][m] = edge_w<T>(r[u], xs, m);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            if (decltype(full)::value || u < n)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    acc[m] = fma_t(w[u][m], v[u][m], acc[m]);
+    };
+    int e = e_lo;
+    for (; e + kChunk <= e_hi; e += kChunk)
+        chunk(std::true_type{}, e, kChunk);
+    if (e < e_hi)
+        chunk(std::false_type{}, e, e_hi - e);
+}
+
+// The final node's sum in binary64.
+template <int K, bool TOGETHER, typename Rec, typename Smp, typename SrcValue>
+__device__ __forceinline__ void final_sum(const Rec *__restrict__ edges, int e_lo, int e_hi, const Smp &xs,
+                                          SrcValue src_value, double (&acc)[K]) {
+    edge_sum<double, K, TOGETHER>(edges, e_lo, e_hi, xs, src_value, acc);
+}
+
+// Interior node of high in-degree (more than kHubEdges in-edges): its edges
+// [e_lo, e_hi) are summed in chunks of kFinalChunk, each the four quarters of
+// kQuarter edges summed sequentially and added as ((q0 + q1) + q2) + q3 (an
+// absent quarter adds T(0)), and the chunk sums added in ascending order to
+// T(0) -- the final node's order, in T.  This is the value every plan gives
+// such a node; the streamed plan computes the chunks in parallel
+// (hub_partial_kernel), the others sequentially with this routine.
+template <typename T, int K, bool TOGETHER, typename Rec, typename Smp, typename SrcValue>
+__device__ __forceinline__ void hub_sum(const Rec *__restrict__ edges, int e_lo, int e_hi, const Smp &xs,
+                                        SrcValue src_value, T (&v)[K]) {
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        v[m] = T(0);
+    for (int c = e_lo; c < e_hi; c += kFinalChunk) {
+        T cs[K];
+#pragma unroll 1
+        for (int i = 0; i < 4; ++i) {
+            const int ql = min(c + i * kQuarter, e_hi);
+            const int qh = min(ql + kQuarter, e_hi);
+            T q[K];
+            edge_sum<T, K, TOGETHER>(edges, ql, qh, xs, src_value, q);
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                cs[m] = i == 0 ? q[m] : cs[m] + q[m];
+        }
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            v[m] = v[m] + cs[m];
+    }
+}
+
+// One wave computes destination rows [jbeg, jend) (at most kWaveRows) of a
+// level for the tile at tbase (64*K samples).  The rows' edges form one
+// contiguous stream, walked in chunks: a chunk's records are fetched together
+// (one scalar wait), its C*K source values requested together (one vector
+// wait), then the factors accumulated.  A row is stored when its flagged last
+// edge has been added; rows without in-edges are stored as zeros.
+//
+// Rows with more than kHubEdges in-edges are taken out of the stream and
+// summed in hub_sum's chunked order: from the chunk sums hub_partial_kernel
+// left in hub_partial ([chunk][ld], the row's chunks starting at the index its
+// first record carries in zero_rows), or, when hub_partial is NULL, by the
+// wave itself.
 //
 // FROM_ROOT: level 1, whose only source is the root (value 1).
 // RESCALE:   binary32 with per-(level, sample) power-of-two scaling: each
@@ -223,13 +307,15 @@ using SampleElem = std::conditional_t<KIND == FK_LOOKUP_T32, float, double>;
 // V:         storage type of the level values (T, or a 16-bit format under
 //            RESCALE): loads widen V to T exactly, stores round T to V.
 // Source rows are reached by 32-bit byte offsets (level buffers < 2 GiB).
+constexpr int kWaveRows = 8;
 template <typename T, int K, bool FROM_ROOT, bool RESCALE, int KIND, typename V = T>
 __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_ptr,
                                                 const typename SweepPath<T, KIND>::Rec *edges, int jbeg, int jend,
                                                 const V *__restrict__ prev, V *__restrict__ cur, int64_t ld,
                                                 int64_t tbase, int lane,
                                                 const typename SweepPath<T, KIND>::template Samples<K> &xs,
-                                                const int (&esh)[K], uint32_t (&lmax)[K]) {
+                                                const int (&esh)[K], uint32_t (&lmax)[K],
+                                                const T *__restrict__ hub_partial = nullptr) {
     using Rec = typename SweepPath<T, KIND>::Rec;
     if (jbeg >= jend)
         return;
@@ -247,70 +333,139 @@ __device__ __forceinline__ void level_wave_rows(const int32_t *__restrict__ row_
         }
     };
     const ConstPtr<int32_t> rp = as_const(row_ptr);
-    int j = jbeg;
-    int e = rp[jbeg];
-    const int e_end = rp[jend];
-    T acc[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m)
-        acc[m] = T(0);
-    // rows without in-edges at the start of the range
-    while (j < jend && rp[j + 1] == e) {
-        store_row(j, acc);
-        ++j;
-    }
-    const Rec *rec = edges + e;
     const char *src_tile = reinterpret_cast<const char *>(prev + tbase);
     const uint32_t row_bytes = static_cast<uint32_t>(ld * sizeof(V));
     const uint32_t lane_off = static_cast<uint32_t>(lane * sizeof(V));
     constexpr int C = kStreamChunk<Rec>;
-    // one chunk of the stream: records, source values and factors, then the
-    // accumulation edge by edge (every edge of a full chunk, the first n of the
-    // tail), storing each row at its flagged last edge
-    auto chunk = [&](auto full, int n) {
-        Rec r[C];
-        load_chunk<C, true>(rec, r);  // past e_end: later edges or the zeroed pad, never used
-        // all C*K source values are requested before any is used; records past
-        // the end name rows inside the level buffer (src < widest level), so
-        // the unused reads stay in bounds
-        T v[C][K];
+
+    // rows [j, j_end), none of high in-degree, as one edge stream
+    auto walk = [&](int j, int j_end) {
+        int e = rp[j];
+        const int e_end = rp[j_end];
+        T acc[K];
 #pragma unroll
-        for (int u = 0; u < C; ++u) {
-            const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                v[u][m] = FROM_ROOT ? T(1) : static_cast<T>(*reinterpret_cast<const V *>(row + m * kWave * sizeof(V)));
+        for (int m = 0; m < K; ++m)
+            acc[m] = T(0);
+        // rows without in-edges at the start of the range
+        while (j < j_end && rp[j + 1] == e) {
+            store_row(j, acc);
+            ++j;
         }
-        T w[C][K];
+        const Rec *rec = edges + e;
+        // one chunk of the stream: records, source values and factors, then the
+        // accumulation edge by edge (every edge of a full chunk, the first n of the
+        // tail), storing each row at its flagged last edge
+        auto chunk = [&](auto full, int n) {
+            Rec r[C];
+            load_chunk<C, true>(rec, r);  // past e_end: later edges or the zeroed pad, never used
+            // all C*K source values are requested before any is used; records past
+            // the end name rows inside the level buffer (src < widest level), so
+            // the unused reads stay in bounds
+            T v[C][K];
 #pragma unroll
-        for (int u = 0; u < C; ++u)
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                w[u][m] = edge_w<T>(r[u], xs, m);
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-            if (decltype(full)::value || u < n) {
+            for (int u = 0; u < C; ++u) {
+                const char *row = src_tile + static_cast<uint32_t>(r[u].src) * row_bytes + lane_off;
 #pragma unroll
                 for (int m = 0; m < K; ++m)
-                    acc[m] = fma_t(w[u][m], v[u][m], acc[m]);
-                if (r[u].row_end) {
-                    store_row(j, acc);
-                    ++j;
+                    v[u][m] = FROM_ROOT ? T(1)
+                                        : static_cast<T>(*reinterpret_cast<const V *>(row + m * kWave * sizeof(V)));
+            }
+            T w[C][K];
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    w[u][m] = edge_w<T>(r[u], xs, m);
+#pragma unroll
+            for (int u = 0; u < C; ++u) {
+                if (decltype(full)::value || u < n) {
 #pragma unroll
                     for (int m = 0; m < K; ++m)
-                        acc[m] = T(0);
-                    for (int z = 0; z < r[u].zero_rows && j < jend; ++z) {
+                        acc[m] = fma_t(w[u][m], v[u][m], acc[m]);
+                    if (r[u].row_end) {
                         store_row(j, acc);
                         ++j;
+#pragma unroll
+                        for (int m = 0; m < K; ++m)
+                            acc[m] = T(0);
+                        for (int z = 0; z < r[u].zero_rows && j < j_end; ++z) {
+                            store_row(j, acc);
+                            ++j;
+                        }
                     }
                 }
             }
-        }
+        };
+        for (; e + C <= e_end; e += C, rec += C)
+            chunk(std::true_type{}, C);
+        if (e < e_end)
+            chunk(std::false_type{}, e_end - e);
     };
-    for (; e + C <= e_end; e += C, rec += C)
-        chunk(std::true_type{}, C);
-    if (e < e_end)
-        chunk(std::false_type{}, e_end - e);
+
+    // a row of high in-degree
+    auto hub_row = [&](int h) {
+        const int e_lo = rp[h], e_hi = rp[h + 1];
+        T v[K];
+        if (hub_partial) {
+            const int cb = as_const(&edges[e_lo].zero_rows)[0];
+            const int nch = (e_hi - e_lo + kFinalChunk - 1) / kFinalChunk;
+            const T *pp = hub_partial + static_cast<int64_t>(cb) * ld + tbase + lane;
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                v[m] = T(0);
+            int c = 0;
+            for (; c + 8 <= nch; c += 8) {  // loads of a group issued together, additions in order
+                T p[8][K];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        p[i][m] = pp[static_cast<int64_t>(c + i) * ld + kWave * m];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        v[m] = v[m] + p[i][m];
+            }
+            for (; c < nch; ++c)
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    v[m] = v[m] + pp[static_cast<int64_t>(c) * ld + kWave * m];
+        } else {
+            hub_sum<T, K, true>(edges, e_lo, e_hi, xs, [&](const Rec &r, int m) -> T {
+                if constexpr (FROM_ROOT) {
+                    return T(1);
+                } else {
+                    const char *row = src_tile + static_cast<uint32_t>(r.src) * row_bytes + lane_off;
+                    return static_cast<T>(*reinterpret_cast<const V *>(row + m * kWave * sizeof(V)));
+                }
+            }, v);
+        }
+        store_row(h, v);
+    };
+
+    // the rows' bounds, fetched together: bit i of hubs marks row jbeg + i as a
+    // row of high in-degree
+    int32_t b[kWaveRows + 1];
+#pragma unroll
+    for (int i = 0; i <= kWaveRows; ++i)
+        b[i] = rp[min(jbeg + i, jend)];
+    uint32_t hubs = 0u;
+#pragma unroll
+    for (int i = 0; i < kWaveRows; ++i)
+        if (b[i + 1] - b[i] > kHubEdges)
+            hubs |= 1u << i;
+    // hub-free stretches walked as streams, each row of high in-degree by itself
+    int j = jbeg;
+    while (true) {
+        const uint32_t ahead = hubs >> (j - jbeg);
+        const int h = ahead ? j + __builtin_ctz(ahead) : jend;
+        walk(j, h);
+        if (h == jend)
+            break;
+        hub_row(h);
+        j = h + 1;
+    }
 }
 
 // Largest |value| bit patterns of NW waves (lmax of each lane) combined in LDS
@@ -332,45 +487,6 @@ __device__ __forceinline__ void fold_max(uint32_t *red /* LDS [NW][64K] */, cons
             atomicMax(cur_max + i, v);
     }
     __syncthreads();
-}
-
-// Sum over final-node edges [e_lo, e_hi) of w_e(x) v_{L-1}[src_e] in binary64,
-// sequentially in canonical order (one quarter of a final-node chunk).  The
-// source value of edge e comes from src_value(rec, m) (level buffer or LDS).
-// Full chunks accumulate unconditionally, a tail its first n edges only.
-template <int K, bool TOGETHER, typename Rec, typename Smp, typename SrcValue>
-__device__ __forceinline__ void final_sum(const Rec *__restrict__ edges, int e_lo, int e_hi, const Smp &xs,
-                                          SrcValue src_value, double (&acc)[K]) {
-#pragma unroll
-    for (int m = 0; m < K; ++m)
-        acc[m] = 0.0;
-    auto chunk = [&](auto full, int e, int n) {
-        Rec r[kChunk];
-        load_chunk<kChunk, TOGETHER>(edges + e, r);
-        double v[kChunk][K];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                v[u][m] = src_value(r[u], m);
-        double w[kChunk][K];
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-#pragma unroll
-            for (int m = 0; m < K; ++m)
-                w[u][m] = edge_w<double>(r[u], xs, m);
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            if (decltype(full)::value || u < n)
-#pragma unroll
-                for (int m = 0; m < K; ++m)
-                    acc[m] = __builtin_fma(w[u][m], v[u][m], acc[m]);
-    };
-    int e = e_lo;
-    for (; e + kChunk <= e_hi; e += kChunk)
-        chunk(std::true_type{}, e, kChunk);
-    if (e < e_hi)
-        chunk(std::false_type{}, e, e_hi - e);
 }
 
 // final_sum with the level L-1 values in a level buffer (streamed kernels; the
@@ -487,6 +603,8 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T, KIND>::Re
                                            const int (&esh)[K], T (&acc)[RMAX][K], uint32_t (&lmax)[K]) {
     using Rec = typename SweepPath<T, KIND>::Rec;
     constexpr int kTile = kWave * K;
+    static_assert(RMAX <= 64, "row mask of 64 bits");
+    uint64_t hubs = 0u;  // bit r: row jb + r has more than kHubEdges in-edges
 #pragma unroll
     for (int m = 0; m < K; ++m)
         lmax[m] = 0u;
@@ -524,6 +642,10 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T, KIND>::Re
                             acc[r][m] = fma_t(w[u][m], v[u][m], acc[r][m]);
             };
             int e = __builtin_amdgcn_readlane(rpl, r);
+            if (e1 - e > kHubEdges) {  // high in-degree: summed below, in hub_sum's order
+                hubs |= uint64_t(1) << r;
+                continue;
+            }
             for (; e + kChunk <= e1; e += kChunk)
                 chunk(std::true_type{}, e, kChunk);
             if (e < e1)
@@ -535,6 +657,27 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T, KIND>::Re
                     lmax[m] = max(lmax[m], abs_bits(acc[r][m]));
                 }
             }
+        }
+    }
+    // rows of high in-degree, one at a time (outside the unrolled loop)
+    while (hubs) {
+        const int r = __builtin_ctzll(hubs);
+        hubs &= hubs - 1;
+        T v[K];
+        hub_sum<T, K, false>(edges, __builtin_amdgcn_readlane(rpl, r), __builtin_amdgcn_readlane(rpl, r + 1), xs,
+                             [&](const Rec &rr, int m) -> T {
+                                 return FROM_ROOT ? T(1) : vals[rr.src * kTile + lane + kWave * m];
+                             }, v);
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            if constexpr (RESCALE) {
+                v[m] = scale_pow2(v[m], esh[m]);
+                lmax[m] = max(lmax[m], abs_bits(v[m]));
+            }
+#pragma unroll
+            for (int q = 0; q < RMAX; ++q)
+                if (q == r)
+                    acc[q][m] = v[m];
         }
     }
 }

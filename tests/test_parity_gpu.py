@@ -270,11 +270,39 @@ def _hub_graph(W, fan, rng):
                         rng.uniform(-1, 1, E), rng.uniform(0.5, 2, E), rng.uniform(-1, 1, (E, 3)))
 
 
+def _parallel_hub_graph(W, mult, fan, rng):
+    # as _hub_graph, but the hub takes `mult` parallel edges from each of the W nodes of level 1, so a
+    # narrow graph (one that fits the whole-graph plan) holds a node of W * mult in-edges
+    widths = np.array([1, W, 1, fan, 1])
+    first = np.concatenate([[0], np.cumsum(widths)])
+    n = W * mult
+    src = np.concatenate([np.zeros(W, int), first[1] + np.tile(np.arange(W), mult), np.full(fan, first[2]),
+                          first[3] + np.arange(fan)])
+    dst = np.concatenate([first[1] + np.arange(W), np.full(n, first[2]), first[3] + np.arange(fan),
+                          np.full(fan, first[4])])
+    E = len(src)
+    return LeveledGraph(widths, np.array([W, n, fan, fan]), src.astype(np.int32), dst.astype(np.int32),
+                        rng.uniform(-1, 1, E), rng.uniform(0.5, 2, E), rng.uniform(-1, 1, (E, 3)))
+
+
+def _serve_one(P, G, x, precision):
+    srv = P.Server(1 << 30, 4)
+    gid = srv.add_graph(G)
+    xd = to_dev(x)
+    out = torch.empty(x.shape[1], dtype=torch.float64, device=xd.device)
+    srv.wait(srv.submit(gid, xd, precision, out=out))
+    torch.cuda.synchronize()
+    y = out.cpu().numpy()
+    srv.close()
+    return y
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
-@pytest.mark.parametrize("W", [200, 4096])
+@pytest.mark.parametrize("W", [200, 4096, 32768])
 def test_interior_node_of_high_in_degree(P, precision, W):
-    # one wave sums the hub's W in-edges in order; the result must meet the bar, and where the
-    # graph fits the whole-graph plan both plans must give the same bits
+    # a hub of W in-edges: up to kHubEdges (1024) summed edge after edge by one wave, above it in chunks
+    # of 256 (chunk sums computed by a launch of their own on the streamed plan, by the wave itself in
+    # the serving runtime); the result must meet the bar, and every plan must give the same bits
     rng = np.random.default_rng(W)
     g = _hub_graph(W, 64, rng)
     x = rng.uniform(-1, 1, (3, 300))
@@ -289,6 +317,69 @@ def test_interior_node_of_high_in_degree(P, precision, W):
         assert np.array_equal(yf.view(np.uint64), ys.view(np.uint64))
     else:
         assert W > 1000
+    if precision != "fp32":  # the serving runtime takes FP64 and FP32-rescaled requests
+        yv = _serve_one(P, G.set_path("auto"), x, precision)
+        assert np.array_equal(yv.view(np.uint64), ys.view(np.uint64))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_hub_of_parallel_edges_same_bits_on_every_plan(P, precision):
+    # a hub of 256 * 8 = 2048 in-edges (parallel edges) in a graph narrow enough for the whole-graph
+    # plan: chunked sums on the streamed plan (separate launch), the fused plan and the serving runtime
+    # (each wave by itself) give identical bits, within the bar of the oracle
+    rng = np.random.default_rng(11)
+    g = _parallel_hub_graph(256, 8, 48, rng)
+    x = rng.uniform(-1, 1, (3, 700))
+    V, Q = oracle_ref(g, x)
+    G = graph(P, g)
+    say(f"parallel-edge hub {precision}")
+    ys = gpu_eval(G.set_path("streamed"), x, precision)
+    assert_parity(ys, V, Q, precision, "parallel hub")
+    yf = gpu_eval(G.set_path("fused"), x, precision)
+    assert np.array_equal(yf.view(np.uint64), ys.view(np.uint64))
+    if precision != "fp32":
+        for path in ("fused", "streamed"):
+            yv = _serve_one(P, G.set_path(path), x, precision)
+            assert np.array_equal(yv.view(np.uint64), ys.view(np.uint64)), path
+
+
+def _level_ms(P, G, xd, precision, reps=5):
+    ws = torch.empty(G.workspace_bytes(xd.shape[1], precision), dtype=torch.uint8, device=xd.device)
+    for _ in range(2):
+        G.evaluate(xd, precision, workspace=ws)
+    torch.cuda.synchronize()
+    for k in ("level", "hub"):
+        P.timing_read(k)
+    P.timing_enable(True)
+    for _ in range(reps):
+        G.evaluate(xd, precision, workspace=ws)
+    torch.cuda.synchronize()
+    P.timing_enable(False)
+    return sum(P.timing_read(k)[0] for k in ("level", "hub")) / reps
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32r"])
+def test_hub_of_32768_in_edges_runs_near_the_spread_graph(P, precision):
+    # the same 32768 in-edges into one node, or spread over 4096 nodes of in-degree 8: the interior
+    # launches of the hub graph (chunk sums + levels) must take at most 1.5x those of the spread graph
+    rng = np.random.default_rng(5)
+    W = 32768
+    hub = _hub_graph(W, W, rng)
+    first = np.concatenate([[0], np.cumsum([1, W, 4096, W, 1])])
+    src = np.concatenate([np.zeros(W, int), first[1] + np.arange(W), first[2] + np.arange(W) % 4096,
+                          first[3] + np.arange(W)])
+    dst = np.concatenate([first[1] + np.arange(W), first[2] + np.arange(W) // 8, first[3] + np.arange(W),
+                          np.full(W, first[4])])
+    E = len(src)
+    spread = LeveledGraph(np.array([1, W, 4096, W, 1]), np.array([W, W, W, W]), src.astype(np.int32),
+                          dst.astype(np.int32), rng.uniform(-1, 1, E), rng.uniform(0.5, 2, E),
+                          rng.uniform(-1, 1, (E, 3)))
+    x = rng.uniform(-1, 1, (3, 4096))
+    xd = to_dev(x)
+    t_hub = _level_ms(P, graph(P, hub).set_path("streamed"), xd, precision)
+    t_spread = _level_ms(P, graph(P, spread).set_path("streamed"), xd, precision)
+    say(f"hub 32768 {precision}: {t_hub:.3f} ms vs spread {t_spread:.3f} ms (ratio {t_hub / t_spread:.2f})")
+    assert t_hub <= 1.5 * t_spread
 
 
 def test_transpose_agrees(P):
