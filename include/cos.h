@@ -242,6 +242,33 @@ cos_status cos_evaluate(const cos_graph *g, const double *x_dev, int64_t S, cos_
                         double *out_dev, int32_t *out_exp_dev, void *workspace_dev,
                         uint64_t workspace_bytes, void *stream);
 
+/* Bytes of the fixed device workspace of cos_evaluate_no_alloc (64 MiB). */
+#define COS_NO_ALLOC_SCRATCH_BYTES (64ull << 20)
+
+/*
+ * cos_evaluate for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same evaluation, arguments and results as cos_evaluate, with the workspace
+ * taken from a fixed array of COS_NO_ALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends; the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine) and queues
+ * kernel launches only.
+ *
+ * A streamed-plan sweep that needs more than the array holds runs in sample
+ * chunks that fit it (the same results).  A graph whose plan does not fit at
+ * all -- a fused plan needing more, or fewer than 256 samples per chunk
+ * fitting -- is refused with COS_EINVAL and a message naming both sizes.
+ *
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (other streams, other threads)
+ * race and give undefined results; serialise them.  The first call on a
+ * device looks up the array's device address (thread-safe).
+ * Errors: those of cos_evaluate, and COS_EDEVICE if the array's address cannot
+ * be obtained.
+ */
+cos_status cos_evaluate_no_alloc(const cos_graph *g, const double *x_dev, int64_t S, cos_precision p,
+                                 double *out_dev, int32_t *out_exp_dev, void *stream);
+
 /* Release a graph and its device memory.  Must not race with queued work that
    reads it.  NULL is a no-op.  Errors: COS_EDEVICE if hipFree fails. */
 cos_status cos_destroy_graph(cos_graph *g);

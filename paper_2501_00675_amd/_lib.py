@@ -29,7 +29,7 @@ EXPORTS = [
     "cos_last_error", "cos_build_id", "cos_abi_version", "cos_create_graph", "cos_graph_get_info",
     "cos_graph_export", "cos_evaluate_workspace_size", "cos_evaluate", "cos_destroy_graph",
     "cos_timing_enable", "cos_timing_read", "cos_graph_set_path", "cos_create_graph_lookup",
-    "cos_graph_export_lookup",
+    "cos_graph_export_lookup", "cos_evaluate_no_alloc",
     "cos_server_create", "cos_server_add_graph", "cos_server_submit", "cos_server_poll", "cos_server_wait",
     "cos_server_cancel", "cos_server_get_stats", "cos_server_destroy",
     "cos_mc_workspace_size", "cos_mc_run", "cos_server_fail_admission", "cos_server_read_steps",
@@ -102,6 +102,8 @@ def _bind(lib):
     lib.cos_evaluate_workspace_size.argtypes = [p, i64, i32, ctypes.POINTER(u64)]
     lib.cos_evaluate.restype = i32
     lib.cos_evaluate.argtypes = [p, p, i64, i32, p, p, p, u64, p]
+    lib.cos_evaluate_no_alloc.restype = i32
+    lib.cos_evaluate_no_alloc.argtypes = [p, p, i64, i32, p, p, p]
     lib.cos_destroy_graph.restype = i32
     lib.cos_destroy_graph.argtypes = [p]
     lib.cos_timing_enable.restype = i32

@@ -1,6 +1,9 @@
 // cos_evaluate: plan (fused or streamed, sample chunks), workspace layout and
 // the per-level launch sequence.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "cos_internal.h"
 
@@ -116,52 +119,60 @@ extern "C" cos_status cos_evaluate_workspace_size(const cos_graph *h, int64_t S,
     return COS_OK;
 }
 
-extern "C" cos_status cos_evaluate(const cos_graph *h, const double *x_dev, int64_t S, cos_precision p,
-                                   double *out_dev, int32_t *out_exp_dev, void *workspace_dev,
-                                   uint64_t workspace_bytes, void *stream) {
+namespace {
+
+// The checks and launches of one evaluate call.  ws == NULL: the workspace is
+// allocated and freed in stream order.  `who` prefixes error messages.
+cos_status evaluate_with(const cos_graph *h, const double *x_dev, int64_t S, cos_precision p, double *out_dev,
+                         int32_t *out_exp_dev, void *ws, uint64_t workspace_bytes, hipStream_t st,
+                         const char *who) {
+    const std::string w_ = who;
     if (!h)
-        return fail(COS_EINVAL, "cos_evaluate: graph is NULL");
+        return fail(COS_EINVAL, w_ + ": graph is NULL");
     if (S < 0 || S > (int64_t(1) << 40))
-        return fail(COS_EINVAL, "cos_evaluate: S out of range");
+        return fail(COS_EINVAL, w_ + ": S out of range");
     if (!valid_precision(p))
-        return fail(COS_EINVAL, "cos_evaluate: unknown precision");
+        return fail(COS_EINVAL, w_ + ": unknown precision");
     if (S == 0)
         return COS_OK;
     if (!x_dev || !out_dev)
-        return fail(COS_EINVAL, "cos_evaluate: x or out is NULL");
+        return fail(COS_EINVAL, w_ + ": x or out is NULL");
     const Graph &g = graph_of(h);
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != g.device)
-        return fail(COS_EINVAL, "cos_evaluate: the current device is not the graph's device");
-    if (check_precision_range(g, p, "cos_evaluate") != COS_OK)
+        return fail(COS_EINVAL, w_ + ": the current device is not the graph's device");
+    if (check_precision_range(g, p, who) != COS_OK)
         return COS_EINVAL;
     if (value_bytes(p) == 2 && g.path == COS_PATH_FUSED)
-        return fail(COS_EINVAL, "cos_evaluate: 16-bit level storage runs on the streamed plan only");
+        return fail(COS_EINVAL, w_ + ": 16-bit level storage runs on the streamed plan only");
     if (p == COS_FP16_RESCALED && g.h16.empty())
-        return fail(COS_EINVAL, "cos_evaluate: binary16 storage needs rational factors with level row sums of "
-                                "|a| below 2^110 (use COS_BF16_RESCALED or COS_FP32_RESCALED)");
+        return fail(COS_EINVAL, w_ + ": binary16 storage needs rational factors with level row sums of "
+                                     "|a| below 2^110 (use COS_BF16_RESCALED or COS_FP32_RESCALED)");
     Workspace w = plan_workspace(g, S, p);
     if (w.fused && !fused_fits(g, p))
-        return fail(COS_EINVAL, "cos_evaluate: the fused plan was requested but the graph does not fit in LDS");
+        return fail(COS_EINVAL, w_ + ": the fused plan was requested but the graph does not fit in LDS");
     if (!w.fused && max_chunk(g, p) < kSamplePad)
-        return fail(COS_EINVAL, "cos_evaluate: a level is too wide for the streamed plan");
-    hipStream_t st = static_cast<hipStream_t>(stream);
+        return fail(COS_EINVAL, w_ + ": a level is too wide for the streamed plan");
 
-    void *ws = workspace_dev;
     bool owned = false;
     if (ws) {
         if (reinterpret_cast<uintptr_t>(ws) % 256)
-            return fail(COS_EINVAL, "cos_evaluate: workspace must be 256-byte aligned");
+            return fail(COS_EINVAL, w_ + ": workspace must be 256-byte aligned");
         if (workspace_bytes < w.bytes) {
             // a smaller workspace: sweep in smaller sample chunks that fit in it
             if (w.fused)
-                return fail(COS_EINVAL, "cos_evaluate: workspace smaller than cos_evaluate_workspace_size");
+                return fail(COS_EINVAL, w_ + ": workspace of " + std::to_string(workspace_bytes) +
+                                            " bytes is smaller than the " + std::to_string(w.bytes) +
+                                            " bytes the fused plan needs");
             int64_t c = w.S_pad - kSamplePad;
             while (c >= kSamplePad && layout_for_chunk(g, c, p).bytes > workspace_bytes)
                 c -= kSamplePad;
             if (c < kSamplePad)
-                return fail(COS_EINVAL, "cos_evaluate: workspace too small for even " + std::to_string(kSamplePad) +
-                                            " samples per sweep");
+                return fail(COS_EINVAL, w_ + ": workspace of " + std::to_string(workspace_bytes) +
+                                            " bytes is too small for even " + std::to_string(kSamplePad) +
+                                            " samples per sweep (" +
+                                            std::to_string(layout_for_chunk(g, kSamplePad, p).bytes) +
+                                            " bytes)");
             w = layout_for_chunk(g, c, p);
         }
     } else {
@@ -191,6 +202,55 @@ extern "C" cos_status cos_evaluate(const cos_graph *h, const double *x_dev, int6
             err = ferr;
     }
     if (err != hipSuccess)
-        return hip_fail(err, "cos_evaluate: kernel launch");
+        return hip_fail(err, (w_ + ": kernel launch").c_str());
     return COS_OK;
+}
+
+// Fixed workspace of cos_evaluate_no_alloc, one copy per device.  In host code
+// `scratch` names a host-side stand-in, not device memory: kernels are given
+// the device address hipGetSymbolAddress returns, looked up once per device.
+constexpr uint64_t kScratchBytes = uint64_t(COS_NO_ALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> address of that device's copy of scratch
+
+// The calling thread's current device must be dev.
+cos_status scratch_of_device(int dev, void **ptr) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        const hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess)
+            return hip_fail(err, "cos_evaluate_no_alloc: hipGetSymbolAddress(scratch)");
+        if (p == nullptr || reinterpret_cast<uintptr_t>(p) % 256)
+            return fail(COS_EDEVICE, "cos_evaluate_no_alloc: the scratch array has no usable device address");
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return COS_OK;
+}
+
+}  // namespace
+
+extern "C" cos_status cos_evaluate(const cos_graph *h, const double *x_dev, int64_t S, cos_precision p,
+                                   double *out_dev, int32_t *out_exp_dev, void *workspace_dev,
+                                   uint64_t workspace_bytes, void *stream) {
+    return evaluate_with(h, x_dev, S, p, out_dev, out_exp_dev, workspace_dev, workspace_bytes,
+                         static_cast<hipStream_t>(stream), "cos_evaluate");
+}
+
+extern "C" cos_status cos_evaluate_no_alloc(const cos_graph *h, const double *x_dev, int64_t S, cos_precision p,
+                                            double *out_dev, int32_t *out_exp_dev, void *stream) {
+    if (!h)
+        return fail(COS_EINVAL, "cos_evaluate_no_alloc: graph is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != graph_of(h).device)
+        return fail(COS_EINVAL, "cos_evaluate_no_alloc: the current device is not the graph's device");
+    void *ws = nullptr;
+    const cos_status st = scratch_of_device(dev, &ws);
+    if (st != COS_OK)
+        return st;
+    return evaluate_with(h, x_dev, S, p, out_dev, out_exp_dev, ws, kScratchBytes, static_cast<hipStream_t>(stream),
+                         "cos_evaluate_no_alloc");
 }

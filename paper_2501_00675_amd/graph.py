@@ -167,6 +167,29 @@ class Graph:
                     t.record_stream(st)
         return out
 
+    def evaluate_no_alloc(self, x: torch.Tensor, precision: str = "fp64", out: torch.Tensor | None = None,
+                          out_exp: torch.Tensor | None = None) -> torch.Tensor:
+        """cos_evaluate_no_alloc on the current stream: the library's fixed device workspace instead of an
+        allocated one (the same results as evaluate).  Calls that overlap on one device race on that
+        workspace.  Allocates `out` here only when it is not given."""
+        rows = self.n_inputs
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 2
+                and x.shape[0] == rows and x.is_contiguous()):
+            raise ValueError(f"x must be a contiguous float64 CUDA tensor of shape [{rows}, S]")
+        S = x.shape[1]
+        if out is None:
+            out = torch.empty(S, dtype=torch.float64, device=x.device)
+        if not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= S and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 CUDA tensor with >= S elements")
+        if out_exp is not None and not (out_exp.is_cuda and out_exp.dtype == torch.int32
+                                        and out_exp.numel() >= S and out_exp.is_contiguous()):
+            raise ValueError("out_exp must be a contiguous int32 CUDA tensor with >= S elements")
+        st = torch.cuda.current_stream(x.device)
+        check(LIB.cos_evaluate_no_alloc(self.handle, x.data_ptr(), S, PRECISIONS[precision], out.data_ptr(),
+                                        out_exp.data_ptr() if out_exp is not None else None, st.cuda_stream),
+              "cos_evaluate_no_alloc")
+        return out
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             check(LIB.cos_destroy_graph(self._h.value), "cos_destroy_graph")

@@ -120,6 +120,8 @@ def test_evaluate_rejects_null_and_bad_args():
 
     assert L.LIB.cos_evaluate(None, None, 4, 0, None, None, None, 0, None) == -1
     assert "NULL" in L.LIB.cos_last_error().decode()
+    assert L.LIB.cos_evaluate_no_alloc(None, None, 4, 0, None, None, None) == -1
+    assert "cos_evaluate_no_alloc" in L.LIB.cos_last_error().decode()
     v = ctypes.c_uint64()
     assert L.LIB.cos_evaluate_workspace_size(None, 4, 0, ctypes.byref(v)) == -1
     assert L.LIB.cos_graph_get_info(None, None) == -1
