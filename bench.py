@@ -180,7 +180,7 @@ def run_timed(P, G, xd, precision, steps, warmup):
     for _ in range(warmup):
         G.evaluate(xd, precision, out=out, workspace=ws)
     torch.cuda.synchronize()
-    for k in ("level", "fused", "final_partial", "final_combine", "fill"):
+    for k in ("level", "fused", "final_partial", "final_combine", "fill", "hub"):
         P.timing_read(k)
     P.timing_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -193,16 +193,26 @@ def run_timed(P, G, xd, precision, steps, warmup):
     P.timing_enable(False)
     ms = start.elapsed_time(stop) / steps
     kern = {}
-    for k in ("level", "fused", "final_partial", "final_combine", "fill"):
+    for k in ("level", "fused", "final_partial", "final_combine", "fill", "hub"):
         t, n = P.timing_read(k)
         if n:
             kern[k] = {"total_ms": t, "launches": n, "avg_us": 1000.0 * t / n}
     return ms, kern, out
 
 
-def roofline(g, S_pad, precision, kern, steps, workload, copy_gbs=None):
+def level_kernel_name(G, precision):
+    """The kernel the interior levels run on: row panels over narrow sample tiles where the library's panel
+    plan applies (binary32 precisions of wide graphs), else the row-streamed gather."""
+    from paper_2501_00675_amd._lib import PRECISIONS
+
+    code = PRECISIONS[precision]
+    return "level_panel_kernel" if code < 3 and (G.info()["panel_mask"] >> code) & 1 else "level_gather_kernel"
+
+
+def roofline(g, S_pad, precision, kern, steps, workload, copy_gbs=None, level_kernel="level_gather_kernel"):
     """Roofline of the dominant kernel class, from its live HIP-event timings.  copy_gbs: the bandwidth a plain
-    device copy reaches on this GPU, reported beside the nominal peak for HBM-bound kernels."""
+    device copy reaches on this GPU, reported beside the nominal peak for HBM-bound kernels; level_kernel: the
+    kernel the interior levels run on."""
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     if dom == "level":
         per_launch = level_bytes(g, S_pad, precision)
@@ -218,7 +228,7 @@ def roofline(g, S_pad, precision, kern, steps, workload, copy_gbs=None):
         else:
             r = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TFLOPS[precision], "unit": "TFLOP/s",
                  "frac": f_a}
-        r.update({"kernel": "level_gather_kernel", "avg_launch_us": kern[dom]["avg_us"],
+        r.update({"kernel": level_kernel, "avg_launch_us": kern[dom]["avg_us"],
                   "launches_per_step": n_launch, "algorithmic_bytes_per_launch": bytes_step / n_launch,
                   "other_term": ({"alu_tflops": alu, "alu_frac": f_a} if r["bound"] == "hbm"
                                  else {"hbm_gbs": hbm, "hbm_frac": f_h})})
@@ -253,6 +263,8 @@ def roofline(g, S_pad, precision, kern, steps, workload, copy_gbs=None):
 KERNEL_SOURCES = {
     "level_gather_kernel": ["kernels_level.hip", "sweep_device.h", "kernels_common.h", "cos_internal.h",
                             "evaluate.cpp", "../_build.py"],
+    "level_panel_kernel": ["kernels_panel.hip", "sweep_device.h", "kernels_common.h", "cos_internal.h",
+                           "evaluate.cpp", "graph.cpp", "../_build.py"],
     "fused_sweep_kernel": ["kernels_fused.hip", "fused_plan.h", "sweep_device.h", "kernels_common.h",
                            "cos_internal.h", "evaluate.cpp", "../_build.py"],
 }
@@ -602,7 +614,8 @@ def extra_leg(P, name, precisions, args, copy_gbs):
         ms, kern, out = run_timed(P, G, xd, p, args.steps, args.warmup)
         res[p] = {"value": g.n_edges * S / (ms / 1000.0), "ms_per_step": ms, "dtype": DTYPE[p],
                   "storage_dtype": STORAGE[p], "kernels": kern,
-                  "roofline": roofline(g, S_pad, p, kern, args.steps, name, copy_gbs)}
+                  "roofline": roofline(g, S_pad, p, kern, args.steps, name, copy_gbs,
+                                       level_kernel_name(G, p))}
         y = out.cpu().numpy()
         full[p] = y
         check["y"][p] = y[idx]
@@ -700,7 +713,8 @@ def main():
                    "L": g.L, "edges": E, "nodes": g.n_nodes, "S": S, "precision": args.precision,
                    "storage_dtype": STORAGE[args.precision], "factor": args.factor, "seed": g.meta.get("seed")},
         "kernels": kern,
-        "roofline": roofline(g, S_pad, args.precision, kern, args.steps, args.workload, copy_gbs),
+        "roofline": roofline(g, S_pad, args.precision, kern, args.steps, args.workload, copy_gbs,
+                             level_kernel_name(G, args.precision)),
         "copy_calibration": copy,
     }
     variants = {}
@@ -710,7 +724,8 @@ def main():
         msv, kv, outv = run_timed(P, G, xd, pv, args.steps, args.warmup)
         variants[pv] = {"value": E * S / (msv / 1000.0), "ms_per_step": msv, "dtype": DTYPE[pv],
                         "storage_dtype": STORAGE[pv], "kernels": kv,
-                        "roofline": roofline(g, S_pad, pv, kv, args.steps, args.workload, copy_gbs),
+                        "roofline": roofline(g, S_pad, pv, kv, args.steps, args.workload, copy_gbs,
+                                             level_kernel_name(G, pv)),
                         "_y": outv.cpu().numpy()}
     if "fp64" in variants:
         variants["fp64"]["speed_ratio_headline_over_fp64"] = value / variants["fp64"]["value"]

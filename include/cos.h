@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define COS_ABI_VERSION 3
+#define COS_ABI_VERSION 4
 
 typedef enum cos_status {
     COS_OK = 0,
@@ -84,9 +84,12 @@ typedef struct cos_graph cos_graph;
 
 /* Kernel plan of cos_evaluate (see cos_graph_set_path). */
 typedef enum cos_path {
-    COS_PATH_AUTO = 0,     /* fused when the widest level fits in LDS, else streamed */
+    COS_PATH_AUTO = 0,     /* fused when the widest level fits in LDS, else panel where it applies,
+                              else streamed */
     COS_PATH_STREAMED = 1, /* one launch per level, level values streamed through HBM */
-    COS_PATH_FUSED = 2     /* one launch for the whole graph, level values held in LDS */
+    COS_PATH_FUSED = 2,    /* one launch for the whole graph, level values held in LDS */
+    COS_PATH_PANEL = 3     /* streamed, binary32 precisions of wide graphs: row panels with their edge
+                              records in LDS swept over narrow sample tiles kept in L2 */
 } cos_path;
 
 typedef struct cos_graph_info {
@@ -100,6 +103,8 @@ typedef struct cos_graph_info {
     uint64_t device_bytes;   /* device memory held by the graph */
     int32_t factor_kind;     /* COS_FACTOR_RATIONAL or COS_FACTOR_LOOKUP */
     int32_t n_inputs;        /* rows of the per-sample input x_dev: 3, or n_slots */
+    int32_t panel_mask;      /* bit p set: the panel plan applies for cos_precision p */
+    int32_t reserved;
 } cos_graph_info;
 
 /* Edge-factor kinds. */

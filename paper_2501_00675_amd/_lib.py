@@ -34,7 +34,7 @@ EXPORTS = [
     "cos_server_cancel", "cos_server_get_stats", "cos_server_destroy",
     "cos_mc_workspace_size", "cos_mc_run", "cos_server_fail_admission", "cos_server_read_steps",
 ]
-PATHS = {"auto": 0, "streamed": 1, "fused": 2}
+PATHS = {"auto": 0, "streamed": 1, "fused": 2, "panel": 3}
 FACTOR_KINDS = {0: "rational", 1: "lookup"}
 
 
@@ -48,7 +48,8 @@ class GraphInfo(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("fused_mask", ctypes.c_int32), ("n_nodes", ctypes.c_int64),
                 ("n_edges", ctypes.c_int64), ("max_width", ctypes.c_int64), ("max_in_degree", ctypes.c_int64),
                 ("final_in_degree", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
-                ("factor_kind", ctypes.c_int32), ("n_inputs", ctypes.c_int32)]
+                ("factor_kind", ctypes.c_int32), ("n_inputs", ctypes.c_int32), ("panel_mask", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ReqStats(ctypes.Structure):

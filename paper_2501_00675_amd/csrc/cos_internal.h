@@ -78,6 +78,13 @@ struct LevelDesc {
     // in zero_rows, the index of its first chunk relative to hub_begin
     int64_t hub_begin = 0;
     int64_t n_hub_chunks = 0;
+    // panel plan (interior levels): panels [panel_begin, panel_begin + n_panels)
+    // of Graph::d_panels, the first n_panel_half0 covering the first half of
+    // the rows; panel_lds: the largest panel's LDS bytes
+    int64_t panel_begin = 0;
+    int64_t n_panel_half0 = 0;
+    int64_t n_panels = 0;
+    int64_t panel_lds = 0;
 };
 
 // Compact level table read by the fused kernel (device copy).
@@ -86,6 +93,8 @@ struct LevelDev {
     int32_t rp_begin;
     int32_t e_begin;
     int32_t n_edges;
+    int32_t hubs;  // 1 if an interior level has a node of more than kHubEdges in-edges
+    int32_t pad[3];
 };
 
 struct Graph {
@@ -120,6 +129,8 @@ struct Graph {
     LevelDev *d_levels = nullptr;     // L entries
     int32_t *d_h16 = nullptr;         // h16 on the device (L entries; NULL when h16 is empty)
     int32_t *d_hub_chunks = nullptr;  // (first edge, end edge) pairs of the chunks of high in-degree rows
+    bool panel_ok = false;            // every interior level has a panel table (binary32 panel plan)
+    int32_t *d_panels = nullptr;      // (first row, end row, first edge, end edge) per panel, level after level
     int64_t max_hub_chunks = 0;       // most chunks of such rows in one level
     int device = 0;
     cos_path path = COS_PATH_AUTO;    // kernel plan chosen by cos_graph_set_path
@@ -161,6 +172,19 @@ constexpr int kQuarter = kFinalChunk / 4;
 // An interior node with more in-edges than this is summed in chunks of
 // kFinalChunk edges (the final node's order) instead of edge after edge.
 constexpr int kHubEdges = 1024;
+// Panel plan: samples per tile of the tile-major level buffers, threads per
+// workgroup, LDS a panel's records and row offsets may take, and the narrowest
+// level width for which the plan is built (narrower levels keep a 256-sample
+// tile's slice in L2 on the plain streamed plan).
+constexpr int kPanelTile = 16;
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelBlockTiles = 16;  // tiles whose samples are staged in LDS at a time
+constexpr int kPanelSampleBytes = kPanelBlockTiles * kPanelTile * 16;
+constexpr int64_t kPanelLdsBytes = 160 * 1024 - 256;       // the whole dynamic LDS of a workgroup
+constexpr int64_t kPanelRecBytes = kPanelLdsBytes - kPanelSampleBytes;  // a panel's records and offsets
+constexpr int64_t kPanelMinWidth = 4097;
+constexpr int kPanelMaxRows = 1024;  // rows of one panel (4 per lane)
+constexpr int kPanelPadRecs = 8;     // zeroed records after a panel's own in LDS
 constexpr int kFusedWaves = 16;      // wavefronts per workgroup of the LDS-resident sweep
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -221,9 +245,17 @@ hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev
 // t32[i][s] = fl32(x[i][s]) for s < S, 0 for S <= s < ld (n rows).
 hipError_t launch_table32(const double *x, int64_t xs, int64_t S, int32_t n, float *t32, int64_t ld,
                           hipStream_t s);
+// tile_major: the last interior level is stored [tile][node][kPanelTile] (panel
+// plan), with max_width rows per tile.
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld,
                         const double *x, int64_t S, int64_t xs, const uint32_t *maxbits, double *partial,
-                        int32_t chunks, double *out, int32_t *out_exp, hipStream_t s);
+                        int32_t chunks, double *out, int32_t *out_exp, hipStream_t s, bool tile_major = false);
+// Panel plan: whether it applies to graph g at precision p, and one interior
+// level (level buffers tile-major, ld = the padded sample count).
+bool panel_fits(const Graph &g, cos_precision p);
+hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const float *prev, float *cur, int64_t ld,
+                              const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
+                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
 // A whole run of Monte Carlo walkers (cos_mc_run): state x [3][C], v [C],

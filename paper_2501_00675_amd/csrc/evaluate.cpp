@@ -94,18 +94,25 @@ hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char
         err = launch_fill_u32(maxbits, h1 ? static_cast<uint32_t>(127 + h1) << 23 : 0u, w.S_pad, st);
     if (maxbits && err == hipSuccess)
         err = launch_fill_u32(maxbits + w.S_pad, 0u, static_cast<int64_t>(g.L) * w.S_pad, st);
+    // wide binary32 graphs: level buffers tile-major, levels by row panels (kernels_panel.hip)
+    const bool panel = (g.path == COS_PATH_AUTO || g.path == COS_PATH_PANEL) && panel_fits(g, p);
     const void *prev = nullptr;  // level 0: the root, value 1
     for (int l = 1; l <= g.L - 1 && err == hipSuccess; ++l) {
         void *cur = bufs[(l - 1) & 1];
         const uint32_t *pm = maxbits ? maxbits + static_cast<int64_t>(l - 1) * w.S_pad : nullptr;
         uint32_t *cm = (maxbits && l <= g.L - 2) ? maxbits + static_cast<int64_t>(l) * w.S_pad : nullptr;
         const int32_t h_next = l <= g.L - 2 ? headroom(g, p, l + 1) : 0;
-        err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st, t32,
-                           g.max_hub_chunks > 0 ? base + w.off_hub : nullptr);
+        if (panel)
+            err = launch_level_panel(g, l, p, static_cast<const float *>(prev), static_cast<float *>(cur), w.S_pad,
+                                     x, S, xs, pm, cm, st);
+        else
+            err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st, t32,
+                               g.max_hub_chunks > 0 ? base + w.off_hub : nullptr);
         prev = cur;
     }
     if (err == hipSuccess)
-        err = launch_final(g, p, prev, w.S_pad, x, S, xs, maxbits, partial, w.final_chunks, out, out_exp, st);
+        err = launch_final(g, p, prev, w.S_pad, x, S, xs, maxbits, partial, w.final_chunks, out, out_exp, st,
+                           panel && g.L >= 2);
     return err;
 }
 }  // namespace
@@ -151,6 +158,9 @@ cos_status evaluate_with(const cos_graph *h, const double *x_dev, int64_t S, cos
     Workspace w = plan_workspace(g, S, p);
     if (w.fused && !fused_fits(g, p))
         return fail(COS_EINVAL, w_ + ": the fused plan was requested but the graph does not fit in LDS");
+    if (g.path == COS_PATH_PANEL && !panel_fits(g, p))
+        return fail(COS_EINVAL, w_ + ": the panel plan was requested but applies only to binary32 precisions of "
+                                     "wide rational graphs without nodes of more than 1024 in-edges");
     if (!w.fused && max_chunk(g, p) < kSamplePad)
         return fail(COS_EINVAL, w_ + ": a level is too wide for the streamed plan");
 

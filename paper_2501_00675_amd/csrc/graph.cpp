@@ -427,10 +427,66 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
             G.max_hub_chunks = std::max(G.max_hub_chunks, d.n_hub_chunks);
         }
         ldev[l - 1] = LevelDev{static_cast<int32_t>(d.w_dst), static_cast<int32_t>(d.rp_begin),
-                               static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges)};
+                               static_cast<int32_t>(d.e_begin), static_cast<int32_t>(d.n_edges),
+                               d.n_hub_chunks > 0 ? 1 : 0, {0, 0, 0}};
     }
     if (!lookup)
         G.h16 = headroom16(G, row_ptr);
+
+    // panel plan of wide rational graphs without rows of high in-degree: each
+    // interior level's rows in two halves of about equal edge counts, each half
+    // cut into panels of consecutive rows whose records and row offsets fit
+    // the LDS budget, at least 32 per half (one per CU of an XCD) and a
+    // multiple of 32, of about equal edge counts
+    std::vector<int32_t> panels;  // (first row, end row, first edge, end edge)
+    G.panel_ok = !lookup && G.max_hub_chunks == 0 && G.max_width >= kPanelMinWidth && L >= 2;
+    for (int32_t l = 1; l < L && G.panel_ok; ++l) {
+        LevelDesc &d = G.levels[l - 1];
+        const int32_t *r = row_ptr.data() + d.rp_begin;
+        const int64_t W = d.w_dst;
+        d.panel_begin = static_cast<int64_t>(panels.size() / 4);
+        // the first half ends at the first row where half of the level's edges are reached
+        int64_t mid = 0;
+        while (mid < W && 2 * (static_cast<int64_t>(r[mid]) - r[0]) < d.n_edges)
+            ++mid;
+        mid = W > 1 ? std::min<int64_t>(std::max<int64_t>(mid, 1), W - 1) : W;
+        const int64_t halves[3] = {0, mid, W};
+        for (int h = 0; h < 2; ++h) {
+            const int64_t r0 = halves[h], r1 = halves[h + 1];
+            if (r1 <= r0)
+                continue;
+            const int64_t ne = static_cast<int64_t>(r[r1]) - r[r0];
+            const int64_t bytes = (ne + kPanelPadRecs) * 24 + (r1 - r0 + 1) * 4;
+            int64_t n = std::max<int64_t>(32, (bytes + kPanelRecBytes - 1) / kPanelRecBytes);
+            n = (n + 31) / 32 * 32;
+            const int64_t target = std::max<int64_t>(1, (ne + n - 1) / n);
+            int64_t pr = r0;
+            while (pr < r1) {
+                int64_t q = pr, e_in = 0;
+                while (q < r1) {
+                    const int64_t deg = static_cast<int64_t>(r[q + 1]) - r[q];
+                    const int64_t need = (e_in + deg + kPanelPadRecs) * 24 + (q - pr + 2) * 4;
+                    if (q > pr && (e_in + deg > target || need > kPanelRecBytes || q - pr >= kPanelMaxRows))
+                        break;
+                    e_in += deg;
+                    ++q;
+                }
+                const int64_t need = (e_in + kPanelPadRecs) * 24 + (q - pr + 1) * 4;
+                if (need > kPanelRecBytes) {  // one row alone exceeds the budget
+                    G.panel_ok = false;
+                    break;
+                }
+                d.panel_lds = std::max(d.panel_lds, kPanelSampleBytes + need);
+                panels.insert(panels.end(), {static_cast<int32_t>(pr), static_cast<int32_t>(q), r[pr], r[q]});
+                pr = q;
+            }
+            if (h == 0)
+                d.n_panel_half0 = static_cast<int64_t>(panels.size() / 4) - d.panel_begin;
+        }
+        d.n_panels = static_cast<int64_t>(panels.size() / 4) - d.panel_begin;
+    }
+    if (!G.panel_ok)
+        panels.clear();
 
     // one device allocation: row_ptr | edge record arrays | level table
     const size_t off_rp = 0;
@@ -440,7 +496,8 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     const size_t off_lev = off_recL + round_up(recsL.size() * sizeof(EdgeRecL), 256);
     const size_t off_h16 = off_lev + round_up(L * sizeof(LevelDev), 256);
     const size_t off_hub = off_h16 + round_up(G.h16.size() * sizeof(int32_t), 256);
-    const size_t total = off_hub + round_up(hub_chunks.size() * sizeof(int32_t), 256);
+    const size_t off_panel = off_hub + round_up(hub_chunks.size() * sizeof(int32_t), 256);
+    const size_t total = off_panel + round_up(panels.size() * sizeof(int32_t), 256);
     hipError_t err = hipGetDevice(&G.device);
     if (err != hipSuccess)
         return hip_fail(err, "hipGetDevice");
@@ -456,6 +513,7 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     G.d_levels = reinterpret_cast<LevelDev *>(base + off_lev);
     G.d_h16 = G.h16.empty() ? nullptr : reinterpret_cast<int32_t *>(base + off_h16);
     G.d_hub_chunks = hub_chunks.empty() ? nullptr : reinterpret_cast<int32_t *>(base + off_hub);
+    G.d_panels = panels.empty() ? nullptr : reinterpret_cast<int32_t *>(base + off_panel);
     err = hipMemcpy(G.d_row_ptr, row_ptr.data(), rp * sizeof(int32_t), hipMemcpyHostToDevice);
     if (err == hipSuccess && !recs.empty())
         err = hipMemcpy(G.d_edges, recs.data(), recs.size() * sizeof(EdgeRec), hipMemcpyHostToDevice);
@@ -467,6 +525,8 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
         err = hipMemcpy(G.d_levels, ldev.data(), L * sizeof(LevelDev), hipMemcpyHostToDevice);
     if (err == hipSuccess && G.d_h16)
         err = hipMemcpy(G.d_h16, G.h16.data(), G.h16.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (err == hipSuccess && G.d_panels)
+        err = hipMemcpy(G.d_panels, panels.data(), panels.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (err == hipSuccess && G.d_hub_chunks)
         err = hipMemcpy(G.d_hub_chunks, hub_chunks.data(), hub_chunks.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice);
@@ -521,6 +581,8 @@ extern "C" cos_status cos_graph_get_info(const cos_graph *h, cos_graph_info *inf
     info->L = G.L;
     info->fused_mask = (fused_fits(G, COS_FP64) ? 1 : 0) | (fused_fits(G, COS_FP32_RESCALED) ? 2 : 0) |
                        (fused_fits(G, COS_FP32) ? 4 : 0);
+    info->panel_mask = (panel_fits(G, COS_FP32_RESCALED) ? 2 : 0) | (panel_fits(G, COS_FP32) ? 4 : 0);
+    info->reserved = 0;
     info->n_nodes = G.n_nodes;
     info->n_edges = G.n_edges;
     info->max_width = G.max_width;
@@ -535,7 +597,7 @@ extern "C" cos_status cos_graph_get_info(const cos_graph *h, cos_graph_info *inf
 extern "C" cos_status cos_graph_set_path(cos_graph *h, cos_path path) {
     if (!h)
         return fail(COS_EINVAL, "cos_graph_set_path: graph is NULL");
-    if (path != COS_PATH_AUTO && path != COS_PATH_STREAMED && path != COS_PATH_FUSED)
+    if (path != COS_PATH_AUTO && path != COS_PATH_STREAMED && path != COS_PATH_FUSED && path != COS_PATH_PANEL)
         return fail(COS_EINVAL, "cos_graph_set_path: unknown path");
     h->g.path = path;
     return COS_OK;

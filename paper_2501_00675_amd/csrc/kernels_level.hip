@@ -175,6 +175,37 @@ __global__ __launch_bounds__(kBlock) void final_partial_kernel(
         partial[static_cast<int64_t>(c) * ld + tbase + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
 }
 
+// Final node, pass 1, with level L-1 stored tile-major by the panel plan
+// (binary32 values, rational factors): as final_partial_kernel, sample s of
+// node src being prev[((s / kPanelTile) * wbuf + src) * kPanelTile + s % kPanelTile].
+template <int K>
+__global__ __launch_bounds__(kBlock) void final_partial_tm_kernel(
+    const EdgeRec *__restrict__ edges, int32_t n_edges, int32_t n_chunks, const float *__restrict__ prev,
+    int64_t wbuf, int64_t ld, const double *__restrict__ x, int64_t S, int64_t xs, double *__restrict__ partial) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tile = blockIdx.x / n_chunks;
+    const int c = blockIdx.x - tile * n_chunks;
+    const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
+    LaneSamples<K> smp;
+    smp.load(x, S, xs, tbase, lane);
+    const int c_end = min((c + 1) * kFinalChunk, n_edges);
+    const int e_lo = min(c * kFinalChunk + wave * kQuarter, c_end);
+    const int e_hi = min(e_lo + kQuarter, c_end);
+    double acc[K];
+    final_sum<K, true>(edges, e_lo, e_hi, smp, [&](const EdgeRec &r, int m) -> double {
+        const int64_t s = tbase + lane + kWave * m;
+        return static_cast<double>(prev[((s / kPanelTile) * wbuf + r.src) * kPanelTile + s % kPanelTile]);
+    }, acc);
+    __shared__ double red[4][kWave * K];
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        red[wave][lane + kWave * m] = acc[m];
+    __syncthreads();
+    for (int i = threadIdx.x; i < kWave * K; i += kBlock)
+        partial[static_cast<int64_t>(c) * ld + tbase + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+}
+
 __global__ __launch_bounds__(kBlock) void final_combine_kernel(
     const double *__restrict__ partial, int32_t n_chunks, int64_t S_pad, int64_t S,
     const uint32_t *__restrict__ maxbits, int32_t L, double *__restrict__ out, int32_t *__restrict__ out_exp) {
@@ -399,10 +430,22 @@ hipError_t launch_final_partial(const Graph &g, cos_precision p, const void *pre
 
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld, const double *x, int64_t S,
                         int64_t xs, const uint32_t *maxbits, double *partial, int32_t chunks, double *out,
-                        int32_t *out_exp, hipStream_t s) {
-    hipError_t err = g.kind == FK_LOOKUP
-                         ? launch_final_partial<FK_LOOKUP>(g, p, prev, ld, x, S, xs, partial, chunks, s)
-                         : launch_final_partial<FK_RATIONAL>(g, p, prev, ld, x, S, xs, partial, chunks, s);
+                        int32_t *out_exp, hipStream_t s, bool tile_major) {
+    hipError_t err;
+    if (tile_major) {
+        if (g.kind != FK_RATIONAL || value_bytes(p) != 4 || prev == nullptr)
+            return hipErrorInvalidValue;
+        const LevelDesc &d = g.levels[g.L - 1];
+        const int64_t n_tiles = ld / (kWave * kKFinal);
+        TimedLaunch tl(KK_FINAL_PARTIAL, s);
+        hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal>), dim3(static_cast<unsigned>(n_tiles * chunks)),
+                           dim3(kBlock), 0, s, g.d_edges + d.e_begin, static_cast<int32_t>(d.n_edges), chunks,
+                           static_cast<const float *>(prev), g.max_width, ld, x, S, xs, partial);
+        err = hipGetLastError();
+    } else {
+        err = g.kind == FK_LOOKUP ? launch_final_partial<FK_LOOKUP>(g, p, prev, ld, x, S, xs, partial, chunks, s)
+                                  : launch_final_partial<FK_RATIONAL>(g, p, prev, ld, x, S, xs, partial, chunks, s);
+    }
     if (err != hipSuccess)
         return err;
     TimedLaunch tl(KK_FINAL_COMBINE, s);

@@ -1,0 +1,276 @@
+// Wide levels at binary32: row panels whose edge records sit in LDS, swept over
+// narrow sample tiles of the previous level.
+//
+// On a wide random level every source row is read by about d destinations
+// scattered over the level, so a level kernel whose lanes run along 256
+// samples at a time fetches each source row about d times from beyond L2.  Here
+// the level values are stored tile-major ([tile][node][kPanelTile] binary32,
+// 64 bytes per node and tile), and an XCD sweeps its sample tiles one after the
+// other, so the gathers of a tile fall in that tile's slice of the previous
+// level (width * 64 bytes), a much smaller working set for the XCD's L2.  The
+// edge records cannot stream through L2 once per tile as well, so each
+// workgroup (one per CU) loads a panel of consecutive destination rows with
+// their records into LDS once per level and reuses it for every tile, and the
+// tiles' samples are staged in LDS too: inside a tile a lane reads LDS and
+// issues gathers only, with the gathers of its next row (or of the next tile's
+// first row) in flight while a row is summed.  Level values are written with
+// non-temporal stores.
+//
+// Work split: XCD x (block b runs on XCD b % 8) takes samples of quarter x % 4
+// and the rows of half x / 4; its 32 workgroups take that half's panels in
+// turn.  Within a workgroup, kPanelTile / 4 lanes share a destination row and
+// each lane handles 4 consecutive samples (one 16-byte gather per edge).
+//
+// Arithmetic and order are those of level_wave_rows: per (row, sample) the
+// binary32 factor from the binary32 record and the sample rounded to binary32,
+// accumulated by fused multiply-adds in canonical edge order from 0, then the
+// power-of-two rescale -- the results are bit-identical to the other plans.
+#include <atomic>
+
+#include "sweep_device.h"
+
+namespace cosdag {
+namespace {
+
+// One edge in LDS: the binary32 record without its row flags.
+struct PanelRec {
+    float a, b, k0, k1, k2;
+    int32_t src;
+};
+static_assert(sizeof(PanelRec) == 24, "PanelRec layout");
+
+// A sample of the current block of tiles in LDS: its coordinates rounded to
+// binary32 and the exponent shift of the previous level (0 without rescale).
+struct PanelSample {
+    float x0, x1, x2;
+    int32_t esh;
+};
+static_assert(kPanelSampleBytes == kPanelBlockTiles * kPanelTile * static_cast<int>(sizeof(PanelSample)),
+              "sample block size");
+
+// A lane's rows: a panel holds at most kPanelMaxRows rows, kRowsPerLane per lane.
+constexpr int kRowsPerLane = kPanelMaxRows / (kPanelThreads / (kPanelTile / 4));
+static_assert(kRowsPerLane % 2 == 0, "rows alternate between two gather buffers");
+// Edges of a row gathered together (longer rows take the rest one at a time).
+constexpr int kGroup = 6;
+static_assert(kGroup <= kPanelPadRecs, "a row's group never reads past the padding");
+
+template <bool FROM_ROOT, bool RESCALE>
+__global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
+    const int32_t *__restrict__ panels, int32_t n_half0, int32_t n_panels, const EdgeRec32 *__restrict__ edges,
+    const int32_t *__restrict__ row_ptr, const float *__restrict__ prev, float *__restrict__ cur, int64_t wbuf,
+    int64_t n_tiles, const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
+    uint32_t *__restrict__ cur_max) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ uint32_t tmax[kPanelTile];
+    constexpr int kLpr = kPanelTile / 4;  // lanes per row
+    constexpr int kRowsPerStep = kPanelThreads / kLpr;
+    const int tid = threadIdx.x;
+    const int xcd = static_cast<int>(blockIdx.x % kXcds);
+    const int slot = static_cast<int>(blockIdx.x / kXcds);
+    const int n_slots = static_cast<int>(gridDim.x / kXcds);
+    const int quarter = xcd & 3, half = xcd >> 2;
+    const int64_t tpq = n_tiles / 4;  // tiles of each quarter of the samples
+    const int64_t t0 = quarter * tpq, t1 = t0 + tpq;
+    const int q = tid % kLpr;     // this lane's 4 samples within a tile: 4q .. 4q + 3
+    const int rsub = tid / kLpr;  // this lane's rows in a panel: rsub + i * kRowsPerStep
+    const int p_lo = half ? n_half0 : 0, p_hi = half ? n_panels : n_half0;
+    PanelSample *smp = reinterpret_cast<PanelSample *>(lds);
+    for (int p = p_lo + slot; p < p_hi; p += n_slots) {
+        const ConstPtr<int32_t> pd = as_const(panels) + 4 * p;
+        const int rb = pd[0], re = pd[1], eb = pd[2], ee = pd[3];
+        const int nr = re - rb, ne = ee - eb;
+        // after the sample block: records, kPanelPadRecs zeroed ones (source 0), then the row offsets
+        PanelRec *rec = reinterpret_cast<PanelRec *>(lds + kPanelSampleBytes);
+        int32_t *off = reinterpret_cast<int32_t *>(lds + kPanelSampleBytes +
+                                                   static_cast<size_t>(ne + kPanelPadRecs) * sizeof(PanelRec));
+        __syncthreads();  // the previous panel's records are no longer read
+        for (int i = tid; i < ne + kPanelPadRecs; i += kPanelThreads) {
+            if (i < ne) {
+                const EdgeRec32 &e = edges[eb + i];
+                rec[i] = PanelRec{e.a, e.b, e.k0, e.k1, e.k2, e.src};
+            } else {
+                rec[i] = PanelRec{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0};
+            }
+        }
+        for (int i = tid; i <= nr; i += kPanelThreads)
+            off[i] = row_ptr[rb + i] - eb;
+        __syncthreads();
+        // the lane's rows: their edges in LDS
+        int kb[kRowsPerLane], ke[kRowsPerLane];
+#pragma unroll
+        for (int i = 0; i < kRowsPerLane; ++i) {
+            const int r = rsub + i * kRowsPerStep;
+            kb[i] = r < nr ? off[r] : 0;
+            ke[i] = r < nr ? off[r + 1] : 0;
+        }
+        // source value of LDS edge k for the lane's samples of tile t
+        auto gather = [&](int64_t t, int k) -> float4 {
+            if constexpr (FROM_ROOT)
+                return make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+            else
+                return *reinterpret_cast<const float4 *>(prev + (t * wbuf + rec[k].src) * kPanelTile + 4 * q);
+        };
+        // the first kGroup gathers of row i for tile t, issued unconditionally: records past the row are
+        // later records or the zeroed padding, whose sources are rows of the previous level (never summed)
+        auto issue = [&](int64_t t, int i, float4 (&v)[kGroup]) {
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                v[u] = gather(t, kb[i] + u);
+        };
+        // the gathers of the next row (or of the next tile's first row) are in flight while a row is summed
+        float4 buf[2][kGroup];
+        if (t0 < t1)
+            issue(t0, 0, buf[0]);
+        for (int64_t t = t0; t < t1; ++t) {
+            if ((t - t0) % kPanelBlockTiles == 0) {
+                // the next kPanelBlockTiles tiles' samples into LDS (rounded to binary32, the exponent shift)
+                __syncthreads();  // the previous block is no longer read
+                for (int i = tid; i < kPanelBlockTiles * kPanelTile; i += kPanelThreads) {
+                    const int64_t s = t * kPanelTile + i;
+                    PanelSample v{0.0f, 0.0f, 0.0f, 0};
+                    if (s < S)
+                        v = PanelSample{static_cast<float>(x[s]), static_cast<float>(x[xs + s]),
+                                        static_cast<float>(x[2 * xs + s]), 0};
+                    if (RESCALE && prev_max && s < n_tiles * kPanelTile)
+                        v.esh = ilogb_bits(prev_max[s]);
+                    smp[i] = v;
+                }
+                __syncthreads();
+            }
+            // this lane's samples: LDS reads only, so the gathers in flight are not waited for
+            const PanelSample *ms = smp + ((t - t0) % kPanelBlockTiles) * kPanelTile + 4 * q;
+            float x0[4], x1[4], x2[4];
+            int esh[4];
+            uint32_t lmax[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const PanelSample v = ms[j];
+                x0[j] = v.x0;
+                x1[j] = v.x1;
+                x2[j] = v.x2;
+                esh[j] = v.esh;
+                lmax[j] = 0u;
+            }
+            if (RESCALE && tid < kPanelTile)
+                tmax[tid] = 0u;
+            float *ctile = cur + t * wbuf * kPanelTile + 4 * q;
+#pragma unroll
+            for (int i = 0; i < kRowsPerLane; ++i) {
+                if (i + 1 < kRowsPerLane)
+                    issue(t, i + 1, buf[(i + 1) & 1]);
+                else  // the next tile's first row (on the last tile, an unused repeat of this tile's)
+                    issue(min(t + 1, t1 - 1), 0, buf[0]);
+                float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                // edge k added to the sums when `use` (a select, not a branch: the group's records past the
+                // row are formed and dropped)
+                auto add = [&](int k, float4 v, bool use) {
+                    const PanelRec g = rec[k];
+                    const EdgeRec32 e{g.a, g.b, g.k0, g.k1, g.k2, 0, 0, 0};
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float f = __builtin_fmaf(edge_factor32(e, x0[j], x1[j], x2[j]), vv[j], acc[j]);
+                        acc[j] = use ? f : acc[j];
+                    }
+                };
+#pragma unroll
+                for (int u = 0; u < kGroup; ++u)
+                    add(kb[i] + u, buf[i & 1][u], kb[i] + u < ke[i]);
+                for (int k = kb[i] + kGroup; k < ke[i]; ++k)  // rows of more than kGroup edges
+                    add(k, gather(t, k), true);
+                const int r = rsub + i * kRowsPerStep;
+                if (r < nr) {
+                    float z[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        z[j] = acc[j];
+                        if constexpr (RESCALE) {
+                            z[j] = scale_pow2(z[j], esh[j]);
+                            lmax[j] = max(lmax[j], abs_bits(z[j]));
+                        }
+                    }
+                    using F4 = __attribute__((ext_vector_type(4))) float;
+                    F4 *dst = reinterpret_cast<F4 *>(ctile + static_cast<int64_t>(rb + r) * kPanelTile);
+                    const F4 val = {z[0], z[1], z[2], z[3]};
+                    __builtin_nontemporal_store(val, dst);  // streamed out: L2 keeps the gathered slice
+                }
+            }
+            if constexpr (RESCALE) {
+                if (cur_max) {
+                    // lanes of equal q hold the same samples: combine across the wave, then the workgroup
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        for (int d = kLpr; d < kWave; d *= 2)
+                            lmax[i] = max(lmax[i], static_cast<uint32_t>(__shfl_xor(static_cast<int>(lmax[i]), d)));
+                    __syncthreads();  // tmax cleared
+                    if ((tid & (kWave - 1)) < kLpr)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (lmax[i])
+                                atomicMax(&tmax[4 * q + i], lmax[i]);
+                    __syncthreads();
+                    if (tid < kPanelTile && tmax[tid])
+                        atomicMax(cur_max + t * kPanelTile + tid, tmax[tid]);
+                }
+            }
+        }
+    }
+}
+
+// Allow a panel's dynamic LDS (beyond the default limit) once per instantiation.
+template <bool FROM_ROOT, bool RESCALE>
+hipError_t panel_launch(dim3 grid, size_t lds, hipStream_t s, const int32_t *pan, int32_t n0, int32_t n,
+                        const EdgeRec32 *edges, const int32_t *rp, const float *prev, float *cur, int64_t wbuf,
+                        int64_t n_tiles, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
+                        uint32_t *cur_max) {
+    static std::atomic<bool> attr_set{false};
+    auto kern = level_panel_kernel<FROM_ROOT, RESCALE>;
+    if (!attr_set.load(std::memory_order_acquire)) {
+        const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   static_cast<int>(kPanelLdsBytes));
+        if (err != hipSuccess)
+            return err;
+        attr_set.store(true, std::memory_order_release);  // setting it twice is harmless
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(kPanelThreads), lds, s, pan, n0, n, edges, rp, prev, cur, wbuf, n_tiles, x,
+                       S, xs, prev_max, cur_max);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool panel_fits(const Graph &g, cos_precision p) {
+    return g.panel_ok && (p == COS_FP32 || p == COS_FP32_RESCALED);
+}
+
+hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const float *prev, float *cur, int64_t ld,
+                              const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
+                              hipStream_t s) {
+    const LevelDesc &d = g.levels[l - 1];
+    if (!panel_fits(g, p) || ld % (4 * kPanelTile) != 0 || d.panel_lds > kPanelLdsBytes)
+        return hipErrorInvalidValue;
+    const int64_t n_tiles = ld / kPanelTile;
+    // one workgroup per CU: 32 per XCD
+    const dim3 grid(kXcds * 32);
+    const int32_t *pan = g.d_panels + 4 * d.panel_begin;
+    const int32_t n0 = static_cast<int32_t>(d.n_panel_half0), n = static_cast<int32_t>(d.n_panels);
+    const size_t lds = static_cast<size_t>(d.panel_lds);
+    const int32_t *rp = g.d_row_ptr + d.rp_begin;
+    TimedLaunch tl(KK_LEVEL, s);
+    const EdgeRec32 *e = g.d_edges32;
+    const int64_t wb = g.max_width;
+    if (p == COS_FP32_RESCALED)
+        return prev == nullptr
+                   ? panel_launch<true, true>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x, S, xs,
+                                              prev_max, cur_max)
+                   : panel_launch<false, true>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x, S, xs,
+                                               prev_max, cur_max);
+    return prev == nullptr ? panel_launch<true, false>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x, S,
+                                                       xs, prev_max, cur_max)
+                           : panel_launch<false, false>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x,
+                                                        S, xs, prev_max, cur_max);
+}
+
+}  // namespace cosdag

@@ -131,7 +131,7 @@ extern "C" cos_status cos_mc_run(const cos_graph *h, cos_precision p, int64_t C,
     const dim3 grid(static_cast<unsigned>((C + kBlock - 1) / kBlock));
     hipError_t err = hipSuccess;
     // graphs on the fused plan: the whole run in one launch (persistent walkers)
-    const bool fused = g.path != COS_PATH_STREAMED && fused_fits(g, p);
+    const bool fused = (g.path == COS_PATH_AUTO || g.path == COS_PATH_FUSED) && fused_fits(g, p);
     if (fused) {
         const McArgs a{x_dev, v_dev, xp, vp, C, step0, n_steps, seed, sigma, accepted_dev, acc_dev};
         err = launch_fused(g, p, xp, C, vp, nullptr, s, &a);

@@ -38,9 +38,9 @@ __device__ __forceinline__ ConstPtr<T> as_const(const T *p) {
 // Level table entry i (fields read one by one: a struct cannot be copied
 // through an address-space-qualified reference).
 __device__ __forceinline__ LevelDev load_level(const LevelDev *levels, int i) {
-    static_assert(sizeof(LevelDev) == 4 * sizeof(int32_t), "four int32 fields");
-    const ConstPtr<int32_t> p = as_const(reinterpret_cast<const int32_t *>(levels)) + 4 * i;
-    return LevelDev{p[0], p[1], p[2], p[3]};
+    static_assert(sizeof(LevelDev) == 8 * sizeof(int32_t), "five int32 fields and padding");
+    const ConstPtr<int32_t> p = as_const(reinterpret_cast<const int32_t *>(levels)) + 8 * i;
+    return LevelDev{p[0], p[1], p[2], p[3], p[4], {0, 0, 0}};
 }
 
 // Fetch C consecutive records (C * sizeof(Rec) = 128 or 256 bytes) into scalar
@@ -596,7 +596,7 @@ struct FusedGraph {
 // sums of each row (scaled by 2^-esh when RESCALE) into acc, the largest
 // |stored value| bit pattern into lmax.  rpl: lane i (i <= nb) holds the start
 // of row jb + i.  FROM_ROOT: level 1, whose only source is the root (value 1).
-template <typename T, int K, int RMAX, bool FROM_ROOT, bool RESCALE, int KIND>
+template <typename T, int K, int RMAX, bool FROM_ROOT, bool RESCALE, int KIND, bool HUBS>
 __device__ __forceinline__ void fused_rows(const typename SweepPath<T, KIND>::Rec *edges, const T *vals, int nb,
                                            int rpl, int lane,
                                            const typename SweepPath<T, KIND>::template Samples<K> &xs,
@@ -642,9 +642,11 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T, KIND>::Re
                             acc[r][m] = fma_t(w[u][m], v[u][m], acc[r][m]);
             };
             int e = __builtin_amdgcn_readlane(rpl, r);
-            if (e1 - e > kHubEdges) {  // high in-degree: summed below, in hub_sum's order
-                hubs |= uint64_t(1) << r;
-                continue;
+            if constexpr (HUBS) {
+                if (e1 - e > kHubEdges) {  // high in-degree: summed below, in hub_sum's order
+                    hubs |= uint64_t(1) << r;
+                    continue;
+                }
             }
             for (; e + kChunk <= e1; e += kChunk)
                 chunk(std::true_type{}, e, kChunk);
@@ -660,7 +662,7 @@ __device__ __forceinline__ void fused_rows(const typename SweepPath<T, KIND>::Re
         }
     }
     // rows of high in-degree, one at a time (outside the unrolled loop)
-    while (hubs) {
+    while (HUBS && hubs) {
         const int r = __builtin_ctzll(hubs);
         hubs &= hubs - 1;
         T v[K];
@@ -718,10 +720,18 @@ __device__ __forceinline__ void fused_tile(const FusedGraph &G, int64_t tbase, T
         const int rpl = lane <= nb ? rp[jb + lane] : 0;
         T acc[RMAX][K];
         uint32_t lmax[K];
-        if (l == 1)
-            fused_rows<T, K, RMAX, true, RESCALE, KIND>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
-        else
-            fused_rows<T, K, RMAX, false, RESCALE, KIND>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+        // a level with a node of high in-degree takes the variant that sums such rows in chunks
+        if (l == 1) {
+            if (lv.hubs)
+                fused_rows<T, K, RMAX, true, RESCALE, KIND, true>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+            else
+                fused_rows<T, K, RMAX, true, RESCALE, KIND, false>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+        } else {
+            if (lv.hubs)
+                fused_rows<T, K, RMAX, false, RESCALE, KIND, true>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+            else
+                fused_rows<T, K, RMAX, false, RESCALE, KIND, false>(edges, vals, nb, rpl, lane, xs, esh, acc, lmax);
+        }
         __syncthreads();  // every wave has finished reading level l-1
 #pragma unroll
         for (int r = 0; r < RMAX; ++r)

@@ -81,7 +81,7 @@ class Graph:
         return self._n_inputs
 
     def set_path(self, path: str = "auto") -> "Graph":
-        """Kernel plan for later evaluations: 'auto', 'streamed' or 'fused' (cos_graph_set_path)."""
+        """Kernel plan for later evaluations: 'auto', 'streamed', 'fused' or 'panel' (cos_graph_set_path)."""
         check(LIB.cos_graph_set_path(self.handle, PATHS[path]), "cos_graph_set_path")
         return self
 

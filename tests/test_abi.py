@@ -38,7 +38,7 @@ def test_build_id_matches_sources_and_abi_version():
     from paper_2501_00675_amd import _build
 
     assert P.LIB.cos_build_id().decode() == _build.source_hash()
-    assert P.LIB.cos_abi_version() == 3
+    assert P.LIB.cos_abi_version() == 4
 
 
 def _create(g, **over):

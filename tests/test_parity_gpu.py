@@ -561,3 +561,67 @@ def test_evaluate_captured_in_a_graph_replays_bit_identical(P, name, precision, 
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), eager[i]), f"replay with samples {i}"
         gpu_eval(G, xs[(i + 1) % 4], precision)  # eager work between replays
+
+
+@pytest.mark.parametrize("precision", ["fp32r", "fp32"])
+@pytest.mark.parametrize("S", [300, 1000])
+def test_panel_plan_bit_identical_to_streamed(P, precision, S):
+    # wide levels (8192 nodes): row panels with their records in LDS over 16-sample tiles, level values
+    # tile-major; the same arithmetic and order as the row-streamed kernel, so the same bits
+    g, x = make_config("precision", S=S, width=8192, L=5, degree=6, seed=21)
+    G = graph(P, g)
+    say(f"panel vs streamed {precision} S={S}")
+    yp = gpu_eval(G.set_path("panel"), x, precision)
+    ys = gpu_eval(G.set_path("streamed"), x, precision)
+    assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
+    idx = sample_subset(S, 96, seed=2)
+    V, Q = oracle_ref(g, x, idx)
+    assert_parity(yp[idx], V, Q, precision, "panel")
+
+
+def test_panel_plan_uneven_rows_and_chunked_sweeps(P):
+    # irregular in-degrees (1..13), rows without in-edges, a ragged sample count and a workspace that
+    # forces sweeps of 512 samples: the panel plan keeps the streamed plan's bits
+    rng = np.random.default_rng(8)
+    W, L = 5000, 4
+    g = layered_graph([1] + [W] * (L - 1) + [1], rng.integers(1, 14, L), rng)
+    from workloads import draw_params
+    draw_params(g, rng)
+    keep = np.ones(g.n_edges, bool)
+    l2, l3 = g.level_slices()[1], g.level_slices()[2]
+    keep[l2.start:l2.stop] = rng.random(l2.stop - l2.start) > 0.3  # uneven in-degrees in level 2
+    keep[l3.start:l3.stop] = g.dst[l3] % 97 != 5  # some rows of level 3 lose every in-edge
+    g2 = LeveledGraph(g.widths, np.array([int(keep[s].sum()) for s in g.level_slices()]), g.src[keep],
+                      g.dst[keep], g.a[keep], g.b[keep], g.k[keep])
+    x = rng.uniform(-1, 1, (3, 1500))
+    G = graph(P, g2)
+    ys = gpu_eval(G.set_path("streamed"), x, "fp32r")
+    yp = gpu_eval(G.set_path("panel"), x, "fp32r")
+    assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
+    small = torch.empty(G.workspace_bytes(512, "fp32r"), dtype=torch.uint8, device="cuda:0")
+    yc = gpu_eval(G, x, "fp32r", workspace=small)
+    assert np.array_equal(yc.view(np.uint64), ys.view(np.uint64))
+    V, Q = oracle_ref(g2, x, sample_subset(1500, 64))
+    assert_parity(yp[sample_subset(1500, 64)], V, Q, "fp32r", "panel uneven")
+
+
+def test_panel_plan_refused_where_it_does_not_apply(P):
+    g, x = make_config("precision", S=64, width=8192, L=4, seed=3)
+    G = graph(P, g).set_path("panel")
+    with pytest.raises(P.CosError) as ei:
+        gpu_eval(G, x, "fp64")  # binary64 keeps the row-streamed kernel
+    assert ei.value.status == -1 and "panel" in str(ei.value)
+    gn, xn = make_config("mid", S=64)
+    Gn = graph(P, gn).set_path("panel")
+    with pytest.raises(P.CosError):
+        gpu_eval(Gn, xn, "fp32r")  # narrow graph: no panel plan
+
+
+@pytest.mark.slow
+def test_large_panel_plan_bit_identical_to_streamed(P):
+    g, x = make_config("large")
+    G = graph(P, g)
+    say("large panel vs streamed fp32r")
+    yp = gpu_eval(G.set_path("panel"), x, "fp32r")
+    ys = gpu_eval(G.set_path("streamed"), x, "fp32r")
+    assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
