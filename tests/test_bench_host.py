@@ -76,13 +76,21 @@ def test_counter_lines_are_read_only_for_the_current_sources():
     lines = [l for f in sorted(os.listdir(os.path.join(ROOT, "profiles"))) if f.endswith(".md")
              for l in open(os.path.join(ROOT, "profiles", f)) if l.startswith("pmc:")]
     assert lines, "committed counter lines"
-    for line in lines:
-        kv = dict(item.split("=", 1) for item in line[4:].split())
-        got = bench.profiled_traffic(kv["kernel"], kv["workload"], kv["precision"])
-        if kv["src_id"] == bench.kernel_source_id(kv["kernel"]):
-            want = 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"])
-                             + float(kv["write_kib"]) * float(kv["write_scale"]))
-            assert got == pytest.approx(want)
+    parsed = [dict(item.split("=", 1) for item in line[4:].split()) for line in lines]
+
+    def traffic(kv):
+        return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"])
+                         + float(kv["write_kib"]) * float(kv["write_scale"]))
+
+    # lines taken on the current sources are the ones read; a stale line never is
+    current = {(kv["kernel"], kv["workload"], kv["precision"]): traffic(kv) for kv in parsed
+               if kv["src_id"] == bench.kernel_source_id(kv["kernel"])}
+    assert current, "counter lines for the current kernel sources"
+    for kv in parsed:
+        key = (kv["kernel"], kv["workload"], kv["precision"])
+        got = bench.profiled_traffic(*key)
+        if key in current:
+            assert got == pytest.approx(current[key])
         else:
             assert got is None
     assert bench.profiled_traffic("no_such_kernel", "mid", "fp64") is None
