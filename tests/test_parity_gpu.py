@@ -625,3 +625,49 @@ def test_large_panel_plan_bit_identical_to_streamed(P):
     yp = gpu_eval(G.set_path("panel"), x, "fp32r")
     ys = gpu_eval(G.set_path("streamed"), x, "fp32r")
     assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
+
+
+@pytest.mark.parametrize("precision", ["fp32r", "fp32"])
+@pytest.mark.parametrize("S", [1, 70, 257])
+def test_panel_plan_mixed_widths_and_small_S(P, precision, S):
+    # a wide graph whose other levels are narrow (100 and 3 nodes) and sample counts below one tile
+    # quarter: every level runs on the panel plan, with the streamed plan's bits
+    rng = np.random.default_rng(S)
+    from workloads import draw_params
+    g = layered_graph([1, 5000, 100, 7000, 3, 1], [1, 5, 4, 9, 3], rng, cover=False)
+    draw_params(g, rng)
+    x = rng.uniform(-1, 1, (3, S))
+    G = graph(P, g)
+    assert (G.info()["panel_mask"] >> {"fp32r": 1, "fp32": 2}[precision]) & 1
+    yp = gpu_eval(G.set_path("panel"), x, precision)
+    ys = gpu_eval(G.set_path("streamed"), x, precision)
+    assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
+    V, Q = oracle_ref(g, x)
+    assert_parity(yp, V, Q, precision, f"panel mixed S={S}")
+
+
+def test_panel_plan_captured_in_a_graph_replays_bit_identical(P):
+    # the panel plan queues kernel launches only (and fill kernels), so it can be captured and replayed
+    g, x = make_config("precision", S=2048, width=8192, L=5, degree=6, seed=4)
+    G = graph(P, g).set_path("panel")
+    rng = np.random.default_rng(6)
+    xs = [x] + [x + rng.normal(0, 0.05, x.shape) for _ in range(2)]
+    eager = [gpu_eval(G, xi, "fp32r") for xi in xs]
+    xd = to_dev(xs[0])
+    out = torch.empty(x.shape[1], dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(G.workspace_bytes(x.shape[1], "fp32r"), dtype=torch.uint8, device="cuda:0")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        G.evaluate(xd, "fp32r", out=out, workspace=ws, stream=s)
+    s.synchronize()
+    graph_ = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph_, stream=s):
+        G.evaluate(xd, "fp32r", out=out, workspace=ws, stream=s)
+    for i in (1, 2, 0):
+        xd.copy_(to_dev(xs[i]))
+        torch.cuda.synchronize()
+        graph_.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager[i]), f"replay with samples {i}"
+        gpu_eval(G, xs[(i + 1) % 3], "fp32r")
