@@ -172,18 +172,19 @@ constexpr int kQuarter = kFinalChunk / 4;
 // An interior node with more in-edges than this is summed in chunks of
 // kFinalChunk edges (the final node's order) instead of edge after edge.
 constexpr int kHubEdges = 1024;
-// Panel plan: samples per tile of the tile-major level buffers, threads per
-// workgroup, LDS a panel's records and row offsets may take, and the narrowest
-// level width for which the plan is built (narrower levels keep a 256-sample
-// tile's slice in L2 on the plain streamed plan).
-constexpr int kPanelTile = 16;
+// Panel plan: samples per tile of the tile-major level buffers (a node's
+// binary32 values of a tile fill one 128-byte line), threads per workgroup, LDS
+// a panel's records and row offsets may take, and the narrowest level width for
+// which the plan is built (narrower levels keep a 256-sample tile's slice in L2
+// on the plain streamed plan).
+constexpr int kPanelTile = 32;
 constexpr int kPanelThreads = 1024;
-constexpr int kPanelBlockTiles = 16;  // tiles whose samples are staged in LDS at a time
+constexpr int kPanelBlockTiles = 8;  // tiles whose samples are staged in LDS at a time
 constexpr int kPanelSampleBytes = kPanelBlockTiles * kPanelTile * 16;
 constexpr int64_t kPanelLdsBytes = 160 * 1024 - 256;       // the whole dynamic LDS of a workgroup
 constexpr int64_t kPanelRecBytes = kPanelLdsBytes - kPanelSampleBytes;  // a panel's records and offsets
 constexpr int64_t kPanelMinWidth = 4097;
-constexpr int kPanelMaxRows = 1024;  // rows of one panel (4 per lane)
+constexpr int kPanelMaxRows = 1024;  // rows of one panel (8 per lane)
 constexpr int kPanelPadRecs = 8;     // zeroed records after a panel's own in LDS
 constexpr int kFusedWaves = 16;      // wavefronts per workgroup of the LDS-resident sweep
 

@@ -5,9 +5,10 @@
 // scattered over the level, so a level kernel whose lanes run along 256
 // samples at a time fetches each source row about d times from beyond L2.  Here
 // the level values are stored tile-major ([tile][node][kPanelTile] binary32,
-// 64 bytes per node and tile), and an XCD sweeps its sample tiles one after the
-// other, so the gathers of a tile fall in that tile's slice of the previous
-// level (width * 64 bytes), a much smaller working set for the XCD's L2.  The
+// one 128-byte line per node and tile), and an XCD sweeps its sample tiles one
+// after the other, so the gathers of a tile fall in that tile's slice of the
+// previous level (width * 128 bytes), a much smaller working set for the XCD's
+// L2, and every line fetched is used whole.  The
 // edge records cannot stream through L2 once per tile as well, so each
 // workgroup (one per CU) loads a panel of consecutive destination rows with
 // their records into LDS once per level and reuses it for every tile, and the
@@ -19,7 +20,8 @@
 // Work split: XCD x (block b runs on XCD b % 8) takes samples of quarter x % 4
 // and the rows of half x / 4; its 32 workgroups take that half's panels in
 // turn.  Within a workgroup, kPanelTile / 4 lanes share a destination row and
-// each lane handles 4 consecutive samples (one 16-byte gather per edge).
+// each lane handles 4 consecutive samples (one 16-byte gather per edge); a
+// lane's rows take their edge ranges from the panel's row offsets in LDS.
 //
 // Arithmetic and order are those of level_wave_rows: per (row, sample) the
 // binary32 factor from the binary32 record and the sample rounded to binary32,
@@ -97,13 +99,8 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
             off[i] = row_ptr[rb + i] - eb;
         __syncthreads();
         // the lane's rows: their edges in LDS
-        int kb[kRowsPerLane], ke[kRowsPerLane];
-#pragma unroll
-        for (int i = 0; i < kRowsPerLane; ++i) {
-            const int r = rsub + i * kRowsPerStep;
-            kb[i] = r < nr ? off[r] : 0;
-            ke[i] = r < nr ? off[r + 1] : 0;
-        }
+        auto kbf = [&](int i) { const int r = rsub + i * kRowsPerStep; return r < nr ? off[r] : 0; };
+        auto kef = [&](int i) { const int r = rsub + i * kRowsPerStep; return r < nr ? off[r + 1] : 0; };
         // source value of LDS edge k for the lane's samples of tile t
         auto gather = [&](int64_t t, int k) -> float4 {
             if constexpr (FROM_ROOT)
@@ -116,7 +113,7 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
         auto issue = [&](int64_t t, int i, float4 (&v)[kGroup]) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
-                v[u] = gather(t, kb[i] + u);
+                v[u] = gather(t, kbf(i) + u);
         };
         // the gathers of the next row (or of the next tile's first row) are in flight while a row is summed
         float4 buf[2][kGroup];
@@ -174,10 +171,11 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                         acc[j] = use ? f : acc[j];
                     }
                 };
+                const int kbi = kbf(i), kei = kef(i);
 #pragma unroll
                 for (int u = 0; u < kGroup; ++u)
-                    add(kb[i] + u, buf[i & 1][u], kb[i] + u < ke[i]);
-                for (int k = kb[i] + kGroup; k < ke[i]; ++k)  // rows of more than kGroup edges
+                    add(kbi + u, buf[i & 1][u], kbi + u < kei);
+                for (int k = kbi + kGroup; k < kei; ++k)  // rows of more than kGroup edges
                     add(k, gather(t, k), true);
                 const int r = rsub + i * kRowsPerStep;
                 if (r < nr) {
