@@ -202,11 +202,11 @@ def run_timed(P, G, xd, precision, steps, warmup):
 
 def level_kernel_name(G, precision):
     """The kernel the interior levels run on: row panels over narrow sample tiles where the library's panel
-    plan applies (binary32 precisions of wide graphs), else the row-streamed gather."""
+    plan applies (binary32 and 16-bit storage precisions of wide graphs), else the row-streamed gather."""
     from paper_2501_00675_amd._lib import PRECISIONS
 
     code = PRECISIONS[precision]
-    return "level_panel_kernel" if code < 3 and (G.info()["panel_mask"] >> code) & 1 else "level_gather_kernel"
+    return "level_panel_kernel" if (G.info()["panel_mask"] >> code) & 1 else "level_gather_kernel"
 
 
 def roofline(g, S_pad, precision, kern, steps, workload, copy_gbs=None, level_kernel="level_gather_kernel"):

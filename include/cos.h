@@ -69,14 +69,14 @@ typedef enum cos_precision {
        per-(level, sample) shift also carries a per-level headroom 2^h computed
        at graph creation from the largest row sum of |a_e|, so that no stored
        value can exceed the binary16 range.  Rational factors only (lookup
-       factors have no such bound: COS_EINVAL), streamed plan only.  Storage
+       factors have no such bound: COS_EINVAL), streamed and panel plans.  Storage
        rounding makes it less accurate than binary32 (relative rounding 2^-11
        per stored level; the paper's Sec. IV suggests trading precision for
        speed in this direction). */
     COS_FP16_RESCALED = 3,
     /* the same with bfloat16 storage (relative rounding 2^-8 per stored
        level, binary32's exponent range, no headroom needed); both factor
-       kinds, streamed plan only. */
+       kinds, streamed and panel plans. */
     COS_BF16_RESCALED = 4
 } cos_precision;
 
@@ -88,8 +88,8 @@ typedef enum cos_path {
                               else streamed */
     COS_PATH_STREAMED = 1, /* one launch per level, level values streamed through HBM */
     COS_PATH_FUSED = 2,    /* one launch for the whole graph, level values held in LDS */
-    COS_PATH_PANEL = 3     /* streamed, binary32 precisions of wide graphs: row panels with their edge
-                              records in LDS swept over narrow sample tiles kept in L2 */
+    COS_PATH_PANEL = 3     /* streamed, binary32 and 16-bit storage precisions of wide graphs: row
+                              panels with their edge records in LDS swept over narrow sample tiles */
 } cos_path;
 
 typedef struct cos_graph_info {
@@ -400,7 +400,7 @@ cos_status cos_server_add_graph(cos_server *srv, const cos_graph *g, int32_t *gi
 /*
  * Queue a request: x_dev device float64[3][S], out_dev device float64[S],
  * out_exp_dev device int32[S] or NULL (as for cos_evaluate).  Every precision
- * is served; 16-bit storage runs on the streamed plan, as in cos_evaluate.
+ * is served; 16-bit storage runs on the streamed plan, with cos_evaluate's bits.
  * The caller keeps them alive until the request ends (poll/wait return a
  * final status).  Never blocks.  Errors: COS_EINVAL (unknown gid, S < 1, bad
  * precision or one cos_evaluate would refuse for this graph, S too large for

@@ -172,23 +172,26 @@ constexpr int kQuarter = kFinalChunk / 4;
 // An interior node with more in-edges than this is summed in chunks of
 // kFinalChunk edges (the final node's order) instead of edge after edge.
 constexpr int kHubEdges = 1024;
-// Panel plan: samples per tile of the tile-major level buffers (a node's
-// binary32 values of a tile fill one 128-byte line), threads per workgroup, LDS
-// a panel's records and row offsets may take, and the narrowest level width for
-// which the plan is built (narrower levels keep a 256-sample tile's slice in L2
-// on the plain streamed plan).
-constexpr int kPanelTile = 32;
+// Panel plan: bytes of a node's values in one tile of the tile-major level
+// buffers (one 128-byte line: 32 binary32 or 64 16-bit samples per tile),
+// threads per workgroup, samples staged in LDS at a time, LDS a panel's records
+// and row offsets may take, and the narrowest level width for which the plan is
+// built (narrower levels keep a 256-sample tile's slice in L2 on the plain
+// streamed plan).
+constexpr int kPanelLine = 128;
 constexpr int kPanelThreads = 1024;
-constexpr int kPanelBlockTiles = 8;  // tiles whose samples are staged in LDS at a time
-constexpr int kPanelSampleBytes = kPanelBlockTiles * kPanelTile * 16;
+constexpr int kPanelBlockSamples = 256;
+constexpr int kPanelSampleBytes = kPanelBlockSamples * 16;
 constexpr int64_t kPanelLdsBytes = 160 * 1024 - 256;       // the whole dynamic LDS of a workgroup
 constexpr int64_t kPanelRecBytes = kPanelLdsBytes - kPanelSampleBytes;  // a panel's records and offsets
 constexpr int64_t kPanelMinWidth = 4097;
-constexpr int kPanelMaxRows = 1024;  // rows of one panel (8 per lane)
+constexpr int kPanelMaxRows = 1024;  // rows of one panel (8 per lane at binary32, 16 at 16 bits)
 constexpr int kPanelPadRecs = 8;     // zeroed records after a panel's own in LDS
 constexpr int kFusedWaves = 16;      // wavefronts per workgroup of the LDS-resident sweep
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+// Samples per tile of the panel plan for stored values of vb bytes.
+__host__ __device__ constexpr int panel_tile(int vb) { return kPanelLine / vb; }
 
 // Precisions whose interior levels carry the per-(level, sample) exponent.
 __host__ __device__ inline bool is_rescaled(cos_precision p) {
@@ -246,17 +249,17 @@ hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev
 // t32[i][s] = fl32(x[i][s]) for s < S, 0 for S <= s < ld (n rows).
 hipError_t launch_table32(const double *x, int64_t xs, int64_t S, int32_t n, float *t32, int64_t ld,
                           hipStream_t s);
-// tile_major: the last interior level is stored [tile][node][kPanelTile] (panel
-// plan), with max_width rows per tile.
+// tile_major: the last interior level is stored [tile][node][panel_tile(value
+// bytes)] (panel plan), with max_width rows per tile.
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld,
                         const double *x, int64_t S, int64_t xs, const uint32_t *maxbits, double *partial,
                         int32_t chunks, double *out, int32_t *out_exp, hipStream_t s, bool tile_major = false);
 // Panel plan: whether it applies to graph g at precision p, and one interior
 // level (level buffers tile-major, ld = the padded sample count).
 bool panel_fits(const Graph &g, cos_precision p);
-hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const float *prev, float *cur, int64_t ld,
+hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
                               const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
-                              hipStream_t s);
+                              int32_t h_next, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
 // A whole run of Monte Carlo walkers (cos_mc_run): state x [3][C], v [C],

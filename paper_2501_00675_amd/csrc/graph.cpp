@@ -439,7 +439,9 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     // the LDS budget, at least 32 per half (one per CU of an XCD) and a
     // multiple of 32, of about equal edge counts
     std::vector<int32_t> panels;  // (first row, end row, first edge, end edge)
-    G.panel_ok = !lookup && G.max_hub_chunks == 0 && G.max_width >= kPanelMinWidth && L >= 2;
+    // (a source's byte offset within a tile of the level must fit 32 bits)
+    G.panel_ok = !lookup && G.max_hub_chunks == 0 && G.max_width >= kPanelMinWidth &&
+                 G.max_width < (int64_t{1} << 24) && L >= 2;
     for (int32_t l = 1; l < L && G.panel_ok; ++l) {
         LevelDesc &d = G.levels[l - 1];
         const int32_t *r = row_ptr.data() + d.rp_begin;
@@ -465,13 +467,13 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
                 int64_t q = pr, e_in = 0;
                 while (q < r1) {
                     const int64_t deg = static_cast<int64_t>(r[q + 1]) - r[q];
-                    const int64_t need = (e_in + deg + kPanelPadRecs) * 24 + (q - pr + 2) * 4;
+                    const int64_t need = round_up((e_in + deg + kPanelPadRecs) * 24 + (q - pr + 2) * 4, 16);
                     if (q > pr && (e_in + deg > target || need > kPanelRecBytes || q - pr >= kPanelMaxRows))
                         break;
                     e_in += deg;
                     ++q;
                 }
-                const int64_t need = (e_in + kPanelPadRecs) * 24 + (q - pr + 1) * 4;
+                const int64_t need = round_up((e_in + kPanelPadRecs) * 24 + (q - pr + 1) * 4, 16);
                 if (need > kPanelRecBytes) {  // one row alone exceeds the budget
                     G.panel_ok = false;
                     break;
@@ -581,7 +583,9 @@ extern "C" cos_status cos_graph_get_info(const cos_graph *h, cos_graph_info *inf
     info->L = G.L;
     info->fused_mask = (fused_fits(G, COS_FP64) ? 1 : 0) | (fused_fits(G, COS_FP32_RESCALED) ? 2 : 0) |
                        (fused_fits(G, COS_FP32) ? 4 : 0);
-    info->panel_mask = (panel_fits(G, COS_FP32_RESCALED) ? 2 : 0) | (panel_fits(G, COS_FP32) ? 4 : 0);
+    info->panel_mask = 0;
+    for (const cos_precision p : {COS_FP64, COS_FP32_RESCALED, COS_FP32, COS_FP16_RESCALED, COS_BF16_RESCALED})
+        info->panel_mask |= panel_fits(G, p) ? 1 << p : 0;
     info->reserved = 0;
     info->n_nodes = G.n_nodes;
     info->n_edges = G.n_edges;

@@ -176,11 +176,11 @@ __global__ __launch_bounds__(kBlock) void final_partial_kernel(
 }
 
 // Final node, pass 1, with level L-1 stored tile-major by the panel plan
-// (binary32 values, rational factors): as final_partial_kernel, sample s of
-// node src being prev[((s / kPanelTile) * wbuf + src) * kPanelTile + s % kPanelTile].
-template <int K>
+// (values of type V, rational factors): as final_partial_kernel, sample s of
+// node src being prev[((s / tile) * wbuf + src) * tile + s % tile].
+template <int K, typename V>
 __global__ __launch_bounds__(kBlock) void final_partial_tm_kernel(
-    const EdgeRec *__restrict__ edges, int32_t n_edges, int32_t n_chunks, const float *__restrict__ prev,
+    const EdgeRec *__restrict__ edges, int32_t n_edges, int32_t n_chunks, const V *__restrict__ prev,
     int64_t wbuf, int64_t ld, const double *__restrict__ x, int64_t S, int64_t xs, double *__restrict__ partial) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -195,7 +195,8 @@ __global__ __launch_bounds__(kBlock) void final_partial_tm_kernel(
     double acc[K];
     final_sum<K, true>(edges, e_lo, e_hi, smp, [&](const EdgeRec &r, int m) -> double {
         const int64_t s = tbase + lane + kWave * m;
-        return static_cast<double>(prev[((s / kPanelTile) * wbuf + r.src) * kPanelTile + s % kPanelTile]);
+        constexpr int kTile = panel_tile(sizeof(V));
+        return static_cast<double>(prev[((s / kTile) * wbuf + r.src) * kTile + s % kTile]);
     }, acc);
     __shared__ double red[4][kWave * K];
 #pragma unroll
@@ -433,14 +434,22 @@ hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64
                         int32_t *out_exp, hipStream_t s, bool tile_major) {
     hipError_t err;
     if (tile_major) {
-        if (g.kind != FK_RATIONAL || value_bytes(p) != 4 || prev == nullptr)
+        if (g.kind != FK_RATIONAL || p == COS_FP64 || prev == nullptr)
             return hipErrorInvalidValue;
         const LevelDesc &d = g.levels[g.L - 1];
-        const int64_t n_tiles = ld / (kWave * kKFinal);
+        const dim3 grid(static_cast<unsigned>(ld / (kWave * kKFinal) * chunks));
+        const EdgeRec *e = g.d_edges + d.e_begin;
+        const int32_t ne = static_cast<int32_t>(d.n_edges);
         TimedLaunch tl(KK_FINAL_PARTIAL, s);
-        hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal>), dim3(static_cast<unsigned>(n_tiles * chunks)),
-                           dim3(kBlock), 0, s, g.d_edges + d.e_begin, static_cast<int32_t>(d.n_edges), chunks,
-                           static_cast<const float *>(prev), g.max_width, ld, x, S, xs, partial);
+        if (p == COS_FP16_RESCALED)
+            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, _Float16>), grid, dim3(kBlock), 0, s, e, ne, chunks,
+                               static_cast<const _Float16 *>(prev), g.max_width, ld, x, S, xs, partial);
+        else if (p == COS_BF16_RESCALED)
+            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, __bf16>), grid, dim3(kBlock), 0, s, e, ne, chunks,
+                               static_cast<const __bf16 *>(prev), g.max_width, ld, x, S, xs, partial);
+        else
+            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, float>), grid, dim3(kBlock), 0, s, e, ne, chunks,
+                               static_cast<const float *>(prev), g.max_width, ld, x, S, xs, partial);
         err = hipGetLastError();
     } else {
         err = g.kind == FK_LOOKUP ? launch_final_partial<FK_LOOKUP>(g, p, prev, ld, x, S, xs, partial, chunks, s)

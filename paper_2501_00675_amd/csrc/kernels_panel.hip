@@ -1,12 +1,12 @@
-// Wide levels at binary32: row panels whose edge records sit in LDS, swept over
-// narrow sample tiles of the previous level.
+// Wide levels at binary32 and 16-bit storage: row panels whose edge records sit
+// in LDS, swept over narrow sample tiles of the previous level.
 //
 // On a wide random level every source row is read by about d destinations
 // scattered over the level, so a level kernel whose lanes run along 256
 // samples at a time fetches each source row about d times from beyond L2.  Here
-// the level values are stored tile-major ([tile][node][kPanelTile] binary32,
-// one 128-byte line per node and tile), and an XCD sweeps its sample tiles one
-// after the other, so the gathers of a tile fall in that tile's slice of the
+// the level values are stored tile-major ([tile][node][tile samples], one
+// 128-byte line per node and tile: 32 binary32 or 64 16-bit values), and an
+// XCD sweeps its sample tiles one after the other, so the gathers of a tile fall in that tile's slice of the
 // previous level (width * 128 bytes), a much smaller working set for the XCD's
 // L2, and every line fetched is used whole.  The
 // edge records cannot stream through L2 once per tile as well, so each
@@ -19,14 +19,17 @@
 //
 // Work split: XCD x (block b runs on XCD b % 8) takes samples of quarter x % 4
 // and the rows of half x / 4; its 32 workgroups take that half's panels in
-// turn.  Within a workgroup, kPanelTile / 4 lanes share a destination row and
-// each lane handles 4 consecutive samples (one 16-byte gather per edge); a
-// lane's rows take their edge ranges from the panel's row offsets in LDS.
+// turn.  Within a workgroup, (tile samples) / 4 lanes share a destination row
+// and each lane handles 4 consecutive samples (one 16- or 8-byte gather per
+// edge); a lane's rows take their edge ranges from the panel's row offsets in
+// LDS.
 //
 // Arithmetic and order are those of level_wave_rows: per (row, sample) the
 // binary32 factor from the binary32 record and the sample rounded to binary32,
-// accumulated by fused multiply-adds in canonical edge order from 0, then the
-// power-of-two rescale -- the results are bit-identical to the other plans.
+// accumulated by fused multiply-adds in canonical edge order from 0 over the
+// source values widened exactly to binary32, then the power-of-two rescale and
+// one rounding to the storage type -- the results are bit-identical to the
+// other plans.
 #include <atomic>
 
 #include "sweep_device.h"
@@ -34,10 +37,12 @@
 namespace cosdag {
 namespace {
 
-// One edge in LDS: the binary32 record without its row flags.
+// One edge in LDS: the binary32 record without its row flags, the source as
+// the byte offset of its node's line within a tile's slice of the previous
+// level.
 struct PanelRec {
     float a, b, k0, k1, k2;
-    int32_t src;
+    uint32_t soff;
 };
 static_assert(sizeof(PanelRec) == 24, "PanelRec layout");
 
@@ -47,26 +52,78 @@ struct PanelSample {
     float x0, x1, x2;
     int32_t esh;
 };
-static_assert(kPanelSampleBytes == kPanelBlockTiles * kPanelTile * static_cast<int>(sizeof(PanelSample)),
-              "sample block size");
+static_assert(kPanelSampleBytes == kPanelBlockSamples * static_cast<int>(sizeof(PanelSample)), "sample block size");
 
-// A lane's rows: a panel holds at most kPanelMaxRows rows, kRowsPerLane per lane.
-constexpr int kRowsPerLane = kPanelMaxRows / (kPanelThreads / (kPanelTile / 4));
-static_assert(kRowsPerLane % 2 == 0, "rows alternate between two gather buffers");
 // Edges of a row gathered together (longer rows take the rest one at a time).
 constexpr int kGroup = 6;
 static_assert(kGroup <= kPanelPadRecs, "a row's group never reads past the padding");
 
-template <bool FROM_ROOT, bool RESCALE>
+// A lane's four consecutive values of a node in a tile: loaded as one vector
+// (Raw), widened exactly to binary32, stored rounded once to V.
+template <typename V>
+struct PanelIO;
+template <>
+struct PanelIO<float> {
+    using Raw = float4;
+    static __device__ __forceinline__ void widen(const Raw &r, float (&v)[4]) {
+        v[0] = r.x;
+        v[1] = r.y;
+        v[2] = r.z;
+        v[3] = r.w;
+    }
+    static __device__ __forceinline__ void store(float *p, const float (&z)[4]) {
+        using F4 = __attribute__((ext_vector_type(4))) float;
+        const F4 val = {z[0], z[1], z[2], z[3]};
+        __builtin_nontemporal_store(val, reinterpret_cast<F4 *>(p));  // streamed out: L2 keeps the gathered slice
+    }
+};
+template <typename V>
+struct PanelIO16 {
+    using Raw = uint2;
+    static __device__ __forceinline__ float to_float(uint32_t bits) {
+        return static_cast<float>(__builtin_bit_cast(V, static_cast<uint16_t>(bits)));
+    }
+    static __device__ __forceinline__ void widen(const Raw &r, float (&v)[4]) {
+        v[0] = to_float(r.x & 0xffffu);
+        v[1] = to_float(r.x >> 16);
+        v[2] = to_float(r.y & 0xffffu);
+        v[3] = to_float(r.y >> 16);
+    }
+    static __device__ __forceinline__ void store(V *p, const float (&z)[4]) {
+        uint32_t h[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            h[j] = __builtin_bit_cast(uint16_t, static_cast<V>(z[j]));
+        using U2 = __attribute__((ext_vector_type(2))) uint32_t;
+        const U2 val = {h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+        __builtin_nontemporal_store(val, reinterpret_cast<U2 *>(p));
+    }
+};
+template <>
+struct PanelIO<_Float16> : PanelIO16<_Float16> {};
+template <>
+struct PanelIO<__bf16> : PanelIO16<__bf16> {};
+
+// V: storage type of the level values (binary32, or binary16 / bfloat16 under
+// RESCALE).  h_next: the next level's headroom exponent (binary16), by which
+// this level's largest |value| is raised before it is folded into cur_max.
+template <bool FROM_ROOT, bool RESCALE, typename V>
 __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
     const int32_t *__restrict__ panels, int32_t n_half0, int32_t n_panels, const EdgeRec32 *__restrict__ edges,
-    const int32_t *__restrict__ row_ptr, const float *__restrict__ prev, float *__restrict__ cur, int64_t wbuf,
+    const int32_t *__restrict__ row_ptr, const V *__restrict__ prev, V *__restrict__ cur, int64_t wbuf,
     int64_t n_tiles, const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
-    uint32_t *__restrict__ cur_max) {
+    uint32_t *__restrict__ cur_max, int32_t h_next) {
+    using IO = PanelIO<V>;
+    constexpr int kTile = panel_tile(sizeof(V));       // samples per tile
+    constexpr int kBlockTiles = kPanelBlockSamples / kTile;
+    static_assert(kBlockTiles * kTile == kPanelBlockSamples, "whole tiles per sample block");
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ uint32_t tmax[kPanelTile];
-    constexpr int kLpr = kPanelTile / 4;  // lanes per row
+    __shared__ uint32_t tmax[kTile];
+    constexpr int kLpr = kTile / 4;  // lanes per row
     constexpr int kRowsPerStep = kPanelThreads / kLpr;
+    // a lane's rows: a panel holds at most kPanelMaxRows rows, kRowsPerLane per lane
+    constexpr int kRowsPerLane = kPanelMaxRows / kRowsPerStep;
+    static_assert(kRowsPerLane % 2 == 0, "rows alternate between two gather buffers");
     const int tid = threadIdx.x;
     const int xcd = static_cast<int>(blockIdx.x % kXcds);
     const int slot = static_cast<int>(blockIdx.x / kXcds);
@@ -76,23 +133,26 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
     const int64_t t0 = quarter * tpq, t1 = t0 + tpq;
     const int q = tid % kLpr;     // this lane's 4 samples within a tile: 4q .. 4q + 3
     const int rsub = tid / kLpr;  // this lane's rows in a panel: rsub + i * kRowsPerStep
+    // the lane's bytes in a node's line; sources and stores are reached from a wave-uniform tile base by
+    // 32-bit byte offsets (levels narrower than 2^24 nodes)
+    const uint32_t qoff = static_cast<uint32_t>(q) * 4u * sizeof(V);
     const int p_lo = half ? n_half0 : 0, p_hi = half ? n_panels : n_half0;
-    PanelSample *smp = reinterpret_cast<PanelSample *>(lds);
     for (int p = p_lo + slot; p < p_hi; p += n_slots) {
         const ConstPtr<int32_t> pd = as_const(panels) + 4 * p;
         const int rb = pd[0], re = pd[1], eb = pd[2], ee = pd[3];
         const int nr = re - rb, ne = ee - eb;
         // after the sample block: records, kPanelPadRecs zeroed ones (source 0), then the row offsets
-        PanelRec *rec = reinterpret_cast<PanelRec *>(lds + kPanelSampleBytes);
-        int32_t *off = reinterpret_cast<int32_t *>(lds + kPanelSampleBytes +
-                                                   static_cast<size_t>(ne + kPanelPadRecs) * sizeof(PanelRec));
+        PanelRec *rec = reinterpret_cast<PanelRec *>(lds);
+        const size_t rec_bytes = static_cast<size_t>(ne + kPanelPadRecs) * sizeof(PanelRec);
+        int32_t *off = reinterpret_cast<int32_t *>(lds + rec_bytes);
+        PanelSample *smp = reinterpret_cast<PanelSample *>(lds + ((rec_bytes + (nr + 1) * 4 + 15) & ~size_t(15)));
         __syncthreads();  // the previous panel's records are no longer read
         for (int i = tid; i < ne + kPanelPadRecs; i += kPanelThreads) {
             if (i < ne) {
                 const EdgeRec32 &e = edges[eb + i];
-                rec[i] = PanelRec{e.a, e.b, e.k0, e.k1, e.k2, e.src};
+                rec[i] = PanelRec{e.a, e.b, e.k0, e.k1, e.k2, static_cast<uint32_t>(e.src) * kPanelLine};
             } else {
-                rec[i] = PanelRec{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0};
+                rec[i] = PanelRec{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
             }
         }
         for (int i = tid; i <= nr; i += kPanelThreads)
@@ -101,42 +161,45 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
         // the lane's rows: their edges in LDS
         auto kbf = [&](int i) { const int r = rsub + i * kRowsPerStep; return r < nr ? off[r] : 0; };
         auto kef = [&](int i) { const int r = rsub + i * kRowsPerStep; return r < nr ? off[r + 1] : 0; };
-        // source value of LDS edge k for the lane's samples of tile t
-        auto gather = [&](int64_t t, int k) -> float4 {
+        // source values of LDS edge k for the lane's samples of tile t (level 1: the root's value 1, never
+        // loaded)
+        using Raw = typename IO::Raw;
+        auto gather = [&](int64_t t, int k) -> Raw {
             if constexpr (FROM_ROOT)
-                return make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+                return Raw{};
             else
-                return *reinterpret_cast<const float4 *>(prev + (t * wbuf + rec[k].src) * kPanelTile + 4 * q);
+                return *reinterpret_cast<const Raw *>(reinterpret_cast<const char *>(prev) + t * wbuf * kPanelLine +
+                                                      (rec[k].soff + qoff));
         };
         // the first kGroup gathers of row i for tile t, issued unconditionally: records past the row are
         // later records or the zeroed padding, whose sources are rows of the previous level (never summed)
-        auto issue = [&](int64_t t, int i, float4 (&v)[kGroup]) {
+        auto issue = [&](int64_t t, int i, Raw (&v)[kGroup]) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
                 v[u] = gather(t, kbf(i) + u);
         };
         // the gathers of the next row (or of the next tile's first row) are in flight while a row is summed
-        float4 buf[2][kGroup];
+        Raw buf[2][kGroup];
         if (t0 < t1)
             issue(t0, 0, buf[0]);
         for (int64_t t = t0; t < t1; ++t) {
-            if ((t - t0) % kPanelBlockTiles == 0) {
-                // the next kPanelBlockTiles tiles' samples into LDS (rounded to binary32, the exponent shift)
+            if ((t - t0) % kBlockTiles == 0) {
+                // the next kBlockTiles tiles' samples into LDS (rounded to binary32, the exponent shift)
                 __syncthreads();  // the previous block is no longer read
-                for (int i = tid; i < kPanelBlockTiles * kPanelTile; i += kPanelThreads) {
-                    const int64_t s = t * kPanelTile + i;
+                for (int i = tid; i < kPanelBlockSamples; i += kPanelThreads) {
+                    const int64_t s = t * kTile + i;
                     PanelSample v{0.0f, 0.0f, 0.0f, 0};
                     if (s < S)
                         v = PanelSample{static_cast<float>(x[s]), static_cast<float>(x[xs + s]),
                                         static_cast<float>(x[2 * xs + s]), 0};
-                    if (RESCALE && prev_max && s < n_tiles * kPanelTile)
+                    if (RESCALE && prev_max && s < n_tiles * kTile)
                         v.esh = ilogb_bits(prev_max[s]);
                     smp[i] = v;
                 }
                 __syncthreads();
             }
             // this lane's samples: LDS reads only, so the gathers in flight are not waited for
-            const PanelSample *ms = smp + ((t - t0) % kPanelBlockTiles) * kPanelTile + 4 * q;
+            const PanelSample *ms = smp + ((t - t0) % kBlockTiles) * kTile + 4 * q;
             float x0[4], x1[4], x2[4];
             int esh[4];
             uint32_t lmax[4];
@@ -149,9 +212,9 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                 esh[j] = v.esh;
                 lmax[j] = 0u;
             }
-            if (RESCALE && tid < kPanelTile)
+            if (RESCALE && tid < kTile)
                 tmax[tid] = 0u;
-            float *ctile = cur + t * wbuf * kPanelTile + 4 * q;
+            char *cslice = reinterpret_cast<char *>(cur) + t * wbuf * kPanelLine;  // tile t of this level
 #pragma unroll
             for (int i = 0; i < kRowsPerLane; ++i) {
                 if (i + 1 < kRowsPerLane)
@@ -161,10 +224,12 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                 float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
                 // edge k added to the sums when `use` (a select, not a branch: the group's records past the
                 // row are formed and dropped)
-                auto add = [&](int k, float4 v, bool use) {
+                auto add = [&](int k, const Raw &v, bool use) {
                     const PanelRec g = rec[k];
                     const EdgeRec32 e{g.a, g.b, g.k0, g.k1, g.k2, 0, 0, 0};
-                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    float vv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+                    if constexpr (!FROM_ROOT)
+                        IO::widen(v, vv);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const float f = __builtin_fmaf(edge_factor32(e, x0[j], x1[j], x2[j]), vv[j], acc[j]);
@@ -188,10 +253,7 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                             lmax[j] = max(lmax[j], abs_bits(z[j]));
                         }
                     }
-                    using F4 = __attribute__((ext_vector_type(4))) float;
-                    F4 *dst = reinterpret_cast<F4 *>(ctile + static_cast<int64_t>(rb + r) * kPanelTile);
-                    const F4 val = {z[0], z[1], z[2], z[3]};
-                    __builtin_nontemporal_store(val, dst);  // streamed out: L2 keeps the gathered slice
+                    IO::store(reinterpret_cast<V *>(cslice + (static_cast<uint32_t>(rb + r) * kPanelLine + qoff)), z);
                 }
             }
             if constexpr (RESCALE) {
@@ -201,6 +263,10 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                     for (int i = 0; i < 4; ++i)
                         for (int d = kLpr; d < kWave; d *= 2)
                             lmax[i] = max(lmax[i], static_cast<uint32_t>(__shfl_xor(static_cast<int>(lmax[i]), d)));
+                    if (h_next)  // exact: |value| <= 2^15 and h_next <= 96, and monotone, so the max commutes
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            lmax[i] = abs_bits(ldexpf(__uint_as_float(lmax[i]), h_next));
                     __syncthreads();  // tmax cleared
                     if ((tid & (kWave - 1)) < kLpr)
 #pragma unroll
@@ -208,8 +274,8 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                             if (lmax[i])
                                 atomicMax(&tmax[4 * q + i], lmax[i]);
                     __syncthreads();
-                    if (tid < kPanelTile && tmax[tid])
-                        atomicMax(cur_max + t * kPanelTile + tid, tmax[tid]);
+                    if (tid < kTile && tmax[tid])
+                        atomicMax(cur_max + t * kTile + tid, tmax[tid]);
                 }
             }
         }
@@ -217,13 +283,13 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
 }
 
 // Allow a panel's dynamic LDS (beyond the default limit) once per instantiation.
-template <bool FROM_ROOT, bool RESCALE>
+template <bool FROM_ROOT, bool RESCALE, typename V>
 hipError_t panel_launch(dim3 grid, size_t lds, hipStream_t s, const int32_t *pan, int32_t n0, int32_t n,
-                        const EdgeRec32 *edges, const int32_t *rp, const float *prev, float *cur, int64_t wbuf,
-                        int64_t n_tiles, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
-                        uint32_t *cur_max) {
+                        const EdgeRec32 *edges, const int32_t *rp, const void *prev, void *cur, int64_t wbuf,
+                        int64_t ld, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
+                        uint32_t *cur_max, int32_t h_next) {
     static std::atomic<bool> attr_set{false};
-    auto kern = level_panel_kernel<FROM_ROOT, RESCALE>;
+    auto kern = level_panel_kernel<FROM_ROOT, RESCALE, V>;
     if (!attr_set.load(std::memory_order_acquire)) {
         const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -232,43 +298,62 @@ hipError_t panel_launch(dim3 grid, size_t lds, hipStream_t s, const int32_t *pan
             return err;
         attr_set.store(true, std::memory_order_release);  // setting it twice is harmless
     }
-    hipLaunchKernelGGL(kern, grid, dim3(kPanelThreads), lds, s, pan, n0, n, edges, rp, prev, cur, wbuf, n_tiles, x,
-                       S, xs, prev_max, cur_max);
+    const int64_t n_tiles = ld / panel_tile(sizeof(V));
+    hipLaunchKernelGGL(kern, grid, dim3(kPanelThreads), lds, s, pan, n0, n, edges, rp,
+                       static_cast<const V *>(prev), static_cast<V *>(cur), wbuf, n_tiles, x, S, xs, prev_max,
+                       cur_max, h_next);
     return hipGetLastError();
+}
+
+template <bool RESCALE, typename V>
+hipError_t panel_launch_level(bool root, dim3 grid, size_t lds, hipStream_t s, const int32_t *pan, int32_t n0,
+                              int32_t n, const EdgeRec32 *edges, const int32_t *rp, const void *prev, void *cur,
+                              int64_t wbuf, int64_t ld, const double *x, int64_t S, int64_t xs,
+                              const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next) {
+    return root ? panel_launch<true, RESCALE, V>(grid, lds, s, pan, n0, n, edges, rp, prev, cur, wbuf, ld, x, S, xs,
+                                                 prev_max, cur_max, h_next)
+                : panel_launch<false, RESCALE, V>(grid, lds, s, pan, n0, n, edges, rp, prev, cur, wbuf, ld, x, S, xs,
+                                                  prev_max, cur_max, h_next);
 }
 
 }  // namespace
 
 bool panel_fits(const Graph &g, cos_precision p) {
-    return g.panel_ok && (p == COS_FP32 || p == COS_FP32_RESCALED);
+    return g.panel_ok && (p == COS_FP32 || p == COS_FP32_RESCALED || p == COS_FP16_RESCALED || p == COS_BF16_RESCALED);
 }
 
-hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const float *prev, float *cur, int64_t ld,
+hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
                               const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
-                              hipStream_t s) {
+                              int32_t h_next, hipStream_t s) {
     const LevelDesc &d = g.levels[l - 1];
-    if (!panel_fits(g, p) || ld % (4 * kPanelTile) != 0 || d.panel_lds > kPanelLdsBytes)
+    if (!panel_fits(g, p) || ld % (4 * panel_tile(value_bytes(p))) != 0 || d.panel_lds > kPanelLdsBytes)
         return hipErrorInvalidValue;
-    const int64_t n_tiles = ld / kPanelTile;
     // one workgroup per CU: 32 per XCD
     const dim3 grid(kXcds * 32);
     const int32_t *pan = g.d_panels + 4 * d.panel_begin;
     const int32_t n0 = static_cast<int32_t>(d.n_panel_half0), n = static_cast<int32_t>(d.n_panels);
     const size_t lds = static_cast<size_t>(d.panel_lds);
     const int32_t *rp = g.d_row_ptr + d.rp_begin;
+    const bool root = prev == nullptr;
     TimedLaunch tl(KK_LEVEL, s);
     const EdgeRec32 *e = g.d_edges32;
     const int64_t wb = g.max_width;
-    if (p == COS_FP32_RESCALED)
-        return prev == nullptr
-                   ? panel_launch<true, true>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x, S, xs,
-                                              prev_max, cur_max)
-                   : panel_launch<false, true>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x, S, xs,
-                                               prev_max, cur_max);
-    return prev == nullptr ? panel_launch<true, false>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x, S,
-                                                       xs, prev_max, cur_max)
-                           : panel_launch<false, false>(grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, n_tiles, x,
-                                                        S, xs, prev_max, cur_max);
+    switch (p) {
+    case COS_FP32_RESCALED:
+        return panel_launch_level<true, float>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S, xs,
+                                               prev_max, cur_max, h_next);
+    case COS_FP32:
+        return panel_launch_level<false, float>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S, xs,
+                                                nullptr, nullptr, 0);
+    case COS_FP16_RESCALED:
+        return panel_launch_level<true, _Float16>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S,
+                                                  xs, prev_max, cur_max, h_next);
+    case COS_BF16_RESCALED:
+        return panel_launch_level<true, __bf16>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S, xs,
+                                                prev_max, cur_max, h_next);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace cosdag

@@ -566,7 +566,7 @@ def test_evaluate_captured_in_a_graph_replays_bit_identical(P, name, precision, 
 @pytest.mark.parametrize("precision", ["fp32r", "fp32"])
 @pytest.mark.parametrize("S", [300, 1000])
 def test_panel_plan_bit_identical_to_streamed(P, precision, S):
-    # wide levels (8192 nodes): row panels with their records in LDS over 16-sample tiles, level values
+    # wide levels (8192 nodes): row panels with their records in LDS over 32-sample tiles, level values
     # tile-major; the same arithmetic and order as the row-streamed kernel, so the same bits
     g, x = make_config("precision", S=S, width=8192, L=5, degree=6, seed=21)
     G = graph(P, g)
@@ -577,6 +577,23 @@ def test_panel_plan_bit_identical_to_streamed(P, precision, S):
     idx = sample_subset(S, 96, seed=2)
     V, Q = oracle_ref(g, x, idx)
     assert_parity(yp[idx], V, Q, precision, "panel")
+
+
+@pytest.mark.parametrize("precision", ["fp16r", "bf16r"])
+@pytest.mark.parametrize("S", [1, 300, 1000])
+def test_panel_plan_16bit_bit_identical_to_streamed(P, precision, S):
+    # 16-bit storage: 64-sample tiles (one 128-byte line per node), 16 lanes per row and 8-byte gathers;
+    # the graph with a scaled by 2^16 makes binary16 shift every level after the first by its headroom
+    # (h_next > 0 in the maxima the kernel folds)
+    g, x = make_config("precision", S=S, width=8192, L=5, degree=6, seed=22)
+    for gg in (g, g.with_params(a=g.a * 2.0 ** 16)):
+        G = graph(P, gg)
+        assert (G.info()["panel_mask"] >> P.PRECISIONS[precision]) & 1
+        say(f"panel vs streamed {precision} S={S}")
+        yp = gpu_eval(G.set_path("panel"), x, precision)
+        ys = gpu_eval(G.set_path("streamed"), x, precision)
+        assert np.all(np.isfinite(yp))
+        assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
 
 
 def test_panel_plan_uneven_rows_and_chunked_sweeps(P):
@@ -595,14 +612,16 @@ def test_panel_plan_uneven_rows_and_chunked_sweeps(P):
                       g.dst[keep], g.a[keep], g.b[keep], g.k[keep])
     x = rng.uniform(-1, 1, (3, 1500))
     G = graph(P, g2)
-    ys = gpu_eval(G.set_path("streamed"), x, "fp32r")
-    yp = gpu_eval(G.set_path("panel"), x, "fp32r")
-    assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
-    small = torch.empty(G.workspace_bytes(512, "fp32r"), dtype=torch.uint8, device="cuda:0")
-    yc = gpu_eval(G, x, "fp32r", workspace=small)
-    assert np.array_equal(yc.view(np.uint64), ys.view(np.uint64))
-    V, Q = oracle_ref(g2, x, sample_subset(1500, 64))
-    assert_parity(yp[sample_subset(1500, 64)], V, Q, "fp32r", "panel uneven")
+    for precision in ("fp32r", "fp16r", "bf16r"):
+        ys = gpu_eval(G.set_path("streamed"), x, precision)
+        yp = gpu_eval(G.set_path("panel"), x, precision)
+        assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64)), precision
+        small = torch.empty(G.workspace_bytes(512, precision), dtype=torch.uint8, device="cuda:0")
+        yc = gpu_eval(G, x, precision, workspace=small)
+        assert np.array_equal(yc.view(np.uint64), ys.view(np.uint64)), precision
+        if precision == "fp32r":
+            V, Q = oracle_ref(g2, x, sample_subset(1500, 64))
+            assert_parity(yp[sample_subset(1500, 64)], V, Q, "fp32r", "panel uneven")
 
 
 def test_panel_plan_refused_where_it_does_not_apply(P):
@@ -621,13 +640,14 @@ def test_panel_plan_refused_where_it_does_not_apply(P):
 def test_large_panel_plan_bit_identical_to_streamed(P):
     g, x = make_config("large")
     G = graph(P, g)
-    say("large panel vs streamed fp32r")
-    yp = gpu_eval(G.set_path("panel"), x, "fp32r")
-    ys = gpu_eval(G.set_path("streamed"), x, "fp32r")
-    assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
+    for precision in ("fp32r", "fp16r", "bf16r"):
+        say(f"large panel vs streamed {precision}")
+        yp = gpu_eval(G.set_path("panel"), x, precision)
+        ys = gpu_eval(G.set_path("streamed"), x, precision)
+        assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64)), precision
 
 
-@pytest.mark.parametrize("precision", ["fp32r", "fp32"])
+@pytest.mark.parametrize("precision", ["fp32r", "fp32", "fp16r", "bf16r"])
 @pytest.mark.parametrize("S", [1, 70, 257])
 def test_panel_plan_mixed_widths_and_small_S(P, precision, S):
     # a wide graph whose other levels are narrow (100 and 3 nodes) and sample counts below one tile
@@ -638,12 +658,13 @@ def test_panel_plan_mixed_widths_and_small_S(P, precision, S):
     draw_params(g, rng)
     x = rng.uniform(-1, 1, (3, S))
     G = graph(P, g)
-    assert (G.info()["panel_mask"] >> {"fp32r": 1, "fp32": 2}[precision]) & 1
+    assert (G.info()["panel_mask"] >> P.PRECISIONS[precision]) & 1
     yp = gpu_eval(G.set_path("panel"), x, precision)
     ys = gpu_eval(G.set_path("streamed"), x, precision)
     assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
-    V, Q = oracle_ref(g, x)
-    assert_parity(yp, V, Q, precision, f"panel mixed S={S}")
+    if precision in ("fp32r", "fp32"):  # 16-bit storage: its per-sample bound is checked on the streamed plan
+        V, Q = oracle_ref(g, x)
+        assert_parity(yp, V, Q, precision, f"panel mixed S={S}")
 
 
 def test_panel_plan_captured_in_a_graph_replays_bit_identical(P):
