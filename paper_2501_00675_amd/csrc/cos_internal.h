@@ -182,7 +182,7 @@ constexpr int kPanelLine = 128;
 constexpr int kPanelThreads = 1024;
 constexpr int kPanelBlockSamples = 256;
 constexpr int kPanelSampleBytes = kPanelBlockSamples * 16;
-constexpr int64_t kPanelLdsBytes = 160 * 1024 - 256;       // the whole dynamic LDS of a workgroup
+constexpr int64_t kPanelLdsBytes = 160 * 1024 - 512;       // the dynamic LDS of a workgroup (512 B static)
 constexpr int64_t kPanelRecBytes = kPanelLdsBytes - kPanelSampleBytes;  // a panel's records and offsets
 constexpr int64_t kPanelMinWidth = 4097;
 constexpr int kPanelMaxRows = 1024;  // rows of one panel (8 per lane at binary32, 16 at 16 bits)

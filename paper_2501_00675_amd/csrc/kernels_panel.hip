@@ -118,7 +118,11 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
     constexpr int kBlockTiles = kPanelBlockSamples / kTile;
     static_assert(kBlockTiles * kTile == kPanelBlockSamples, "whole tiles per sample block");
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ uint32_t tmax[kTile];
+    // the workgroup's exponent maxima of a tile, two tables used by alternate tiles: a table is sent out and
+    // cleared after the tile's barrier by the threads that read it, and written again two tiles later, after
+    // the barrier of the tile between, so one barrier per tile orders every access
+    __shared__ uint32_t tmax[2][kTile];
+    static_assert(sizeof(tmax) + kPanelLdsBytes <= 160 * 1024, "static and dynamic LDS within a CU's 160 KiB");
     constexpr int kLpr = kTile / 4;  // lanes per row
     constexpr int kRowsPerStep = kPanelThreads / kLpr;
     // a lane's rows: a panel holds at most kPanelMaxRows rows, kRowsPerLane per lane
@@ -137,6 +141,8 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
     // 32-bit byte offsets (levels narrower than 2^24 nodes)
     const uint32_t qoff = static_cast<uint32_t>(q) * 4u * sizeof(V);
     const int p_lo = half ? n_half0 : 0, p_hi = half ? n_panels : n_half0;
+    if (tid < 2 * kTile)
+        tmax[tid / kTile][tid % kTile] = 0u;  // ordered before use by the panel's first barrier
     for (int p = p_lo + slot; p < p_hi; p += n_slots) {
         const ConstPtr<int32_t> pd = as_const(panels) + 4 * p;
         const int rb = pd[0], re = pd[1], eb = pd[2], ee = pd[3];
@@ -212,8 +218,6 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                 esh[j] = v.esh;
                 lmax[j] = 0u;
             }
-            if (RESCALE && tid < kTile)
-                tmax[tid] = 0u;
             char *cslice = reinterpret_cast<char *>(cur) + t * wbuf * kPanelLine;  // tile t of this level
 #pragma unroll
             for (int i = 0; i < kRowsPerLane; ++i) {
@@ -267,15 +271,18 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
                             lmax[i] = abs_bits(ldexpf(__uint_as_float(lmax[i]), h_next));
-                    __syncthreads();  // tmax cleared
+                    uint32_t *tm = tmax[(t - t0) & 1];
                     if ((tid & (kWave - 1)) < kLpr)
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
                             if (lmax[i])
-                                atomicMax(&tmax[4 * q + i], lmax[i]);
-                    __syncthreads();
-                    if (tid < kTile && tmax[tid])
-                        atomicMax(cur_max + t * kTile + tid, tmax[tid]);
+                                atomicMax(&tm[4 * q + i], lmax[i]);
+                    __syncthreads();  // the tile's maxima are all in
+                    if (tid < kTile) {
+                        if (tm[tid])
+                            atomicMax(cur_max + t * kTile + tid, tm[tid]);
+                        tm[tid] = 0u;
+                    }
                 }
             }
         }
