@@ -6,10 +6,10 @@
 // samples at a time fetches each source row about d times from beyond L2.  Here
 // the level values are stored tile-major ([tile][node][tile samples], one
 // 128-byte line per node and tile: 32 binary32 or 64 16-bit values), and an
-// XCD sweeps its sample tiles one after the other, so the gathers of a tile fall in that tile's slice of the
-// previous level (width * 128 bytes), a much smaller working set for the XCD's
-// L2, and every line fetched is used whole.  The
-// edge records cannot stream through L2 once per tile as well, so each
+// XCD sweeps its sample tiles one after the other, so the gathers of a tile
+// fall in that tile's slice of the previous level (width * 128 bytes), a much
+// smaller working set for the XCD's L2, and every line fetched is used whole.
+// The edge records cannot stream through L2 once per tile as well, so each
 // workgroup (one per CU) loads a panel of consecutive destination rows with
 // their records into LDS once per level and reuses it for every tile, and the
 // tiles' samples are staged in LDS too: inside a tile a lane reads LDS and
@@ -147,7 +147,8 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
         const ConstPtr<int32_t> pd = as_const(panels) + 4 * p;
         const int rb = pd[0], re = pd[1], eb = pd[2], ee = pd[3];
         const int nr = re - rb, ne = ee - eb;
-        // after the sample block: records, kPanelPadRecs zeroed ones (source 0), then the row offsets
+        // LDS: records from address 0 (a row's records are then reached by instruction offsets), kPanelPadRecs
+        // zeroed ones (source 0), the row offsets, then the sample block at the next 16-byte boundary
         PanelRec *rec = reinterpret_cast<PanelRec *>(lds);
         const size_t rec_bytes = static_cast<size_t>(ne + kPanelPadRecs) * sizeof(PanelRec);
         int32_t *off = reinterpret_cast<int32_t *>(lds + rec_bytes);
@@ -226,8 +227,8 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                 else  // the next tile's first row (on the last tile, an unused repeat of this tile's)
                     issue(min(t + 1, t1 - 1), 0, buf[0]);
                 float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                // edge k added to the sums when `use` (a select, not a branch: the group's records past the
-                // row are formed and dropped)
+                // edge k added to the sums when `use` (the group's records past the row are formed and
+                // dropped)
                 auto add = [&](int k, const Raw &v, bool use) {
                     const PanelRec g = rec[k];
                     const EdgeRec32 e{g.a, g.b, g.k0, g.k1, g.k2, 0, 0, 0};
