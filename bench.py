@@ -348,7 +348,8 @@ def lookup_leg(P, args):
         print(f"# lookup {p}", file=sys.stderr, flush=True)
         ms, kern, out = run_timed(P, G, Td, p, args.steps, args.warmup)
         res[p] = {"value": g.n_edges * S / (ms / 1000.0), "ms_per_step": ms, "kernels": kern,
-                  "roofline": roofline(g, S_pad, p, kern, args.steps, args.workload + "_lookup")}
+                  "roofline": roofline(g, S_pad, p, kern, args.steps, args.workload + "_lookup",
+                                       level_kernel=level_kernel_name(G, p))}
         check["y"][p] = out.cpu().numpy()[idx]
     return res, [check]
 

@@ -88,8 +88,9 @@ typedef enum cos_path {
                               else streamed */
     COS_PATH_STREAMED = 1, /* one launch per level, level values streamed through HBM */
     COS_PATH_FUSED = 2,    /* one launch for the whole graph, level values held in LDS */
-    COS_PATH_PANEL = 3     /* streamed, binary32 and 16-bit storage precisions of wide graphs: row
-                              panels with their edge records in LDS swept over narrow sample tiles */
+    COS_PATH_PANEL = 3     /* streamed, binary32 and 16-bit storage precisions of wide graphs (lookup
+                              factors: binary32): row panels with their edge records in LDS swept over
+                              narrow sample tiles */
 } cos_path;
 
 typedef struct cos_graph_info {

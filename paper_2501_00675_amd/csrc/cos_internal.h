@@ -246,9 +246,11 @@ hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev
                         int64_t ld, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
                         uint32_t *cur_max, int32_t h_next, hipStream_t s, const float *t32 = nullptr,
                         void *hub = nullptr);
-// t32[i][s] = fl32(x[i][s]) for s < S, 0 for S <= s < ld (n rows).
+// t32[i][s] = fl32(x[i][s]) for s < S, 0 for S <= s < ld (n rows); tile_major:
+// the same values stored [tile][i][panel_tile(4)] (the binary32 panel plan's
+// tables, one 128-byte line per slot and tile).
 hipError_t launch_table32(const double *x, int64_t xs, int64_t S, int32_t n, float *t32, int64_t ld,
-                          hipStream_t s);
+                          hipStream_t s, bool tile_major = false);
 // tile_major: the last interior level is stored [tile][node][panel_tile(value
 // bytes)] (panel plan), with max_width rows per tile.
 hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64_t ld,
@@ -257,9 +259,10 @@ hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64
 // Panel plan: whether it applies to graph g at precision p, and one interior
 // level (level buffers tile-major, ld = the padded sample count).
 bool panel_fits(const Graph &g, cos_precision p);
+// Lookup factors read t32, the tile-major binary32 tables (launch_table32 with tile_major).
 hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
                               const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
-                              int32_t h_next, hipStream_t s);
+                              int32_t h_next, const float *t32, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
 // A whole run of Monte Carlo walkers (cos_mc_run): state x [3][C], v [C],

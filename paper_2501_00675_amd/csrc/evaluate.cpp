@@ -85,8 +85,11 @@ hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char
     float *t32 = w.table32 ? reinterpret_cast<float *>(base + w.off_table32) : nullptr;
     hipError_t err = hipSuccess;
     // lookup factors at binary32: the chunk's tables rounded once, read by the interior levels
+    // wide graphs at binary32 or 16-bit storage: level buffers tile-major, levels by row panels
+    // (kernels_panel.hip); lookup factors then read the binary32 tables tile-major too
+    const bool panel = (g.path == COS_PATH_AUTO || g.path == COS_PATH_PANEL) && panel_fits(g, p);
     if (t32)
-        err = launch_table32(x, xs, S, g.n_slots, t32, w.S_pad, st);
+        err = launch_table32(x, xs, S, g.n_slots, t32, w.S_pad, st, panel);
     // row 0: the root's value 1 times level 1's headroom 2^h (0 = no shift);
     // rows 1..L: zero, for the atomic max of each level
     const int32_t h1 = g.L >= 2 ? headroom(g, p, 1) : 0;
@@ -94,9 +97,6 @@ hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char
         err = launch_fill_u32(maxbits, h1 ? static_cast<uint32_t>(127 + h1) << 23 : 0u, w.S_pad, st);
     if (maxbits && err == hipSuccess)
         err = launch_fill_u32(maxbits + w.S_pad, 0u, static_cast<int64_t>(g.L) * w.S_pad, st);
-    // wide graphs at binary32 or 16-bit storage: level buffers tile-major, levels by row panels
-    // (kernels_panel.hip)
-    const bool panel = (g.path == COS_PATH_AUTO || g.path == COS_PATH_PANEL) && panel_fits(g, p);
     const void *prev = nullptr;  // level 0: the root, value 1
     for (int l = 1; l <= g.L - 1 && err == hipSuccess; ++l) {
         void *cur = bufs[(l - 1) & 1];
@@ -104,7 +104,7 @@ hipError_t sweep_chunk(const Graph &g, cos_precision p, const Workspace &w, char
         uint32_t *cm = (maxbits && l <= g.L - 2) ? maxbits + static_cast<int64_t>(l) * w.S_pad : nullptr;
         const int32_t h_next = l <= g.L - 2 ? headroom(g, p, l + 1) : 0;
         if (panel)
-            err = launch_level_panel(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st);
+            err = launch_level_panel(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, t32, st);
         else
             err = launch_level(g, l, p, prev, cur, w.S_pad, x, S, xs, pm, cm, h_next, st, t32,
                                g.max_hub_chunks > 0 ? base + w.off_hub : nullptr);
@@ -159,9 +159,9 @@ cos_status evaluate_with(const cos_graph *h, const double *x_dev, int64_t S, cos
     if (w.fused && !fused_fits(g, p))
         return fail(COS_EINVAL, w_ + ": the fused plan was requested but the graph does not fit in LDS");
     if (g.path == COS_PATH_PANEL && !panel_fits(g, p))
-        return fail(COS_EINVAL, w_ + ": the panel plan was requested but applies only to binary32 and 16-bit "
-                                     "storage precisions of wide rational graphs without nodes of more than 1024 "
-                                     "in-edges");
+        return fail(COS_EINVAL, w_ + ": the panel plan was requested but applies only to graphs wider than 4096 "
+                                     "nodes without nodes of more than 1024 in-edges, at binary32 and (rational "
+                                     "factors) 16-bit storage precisions");
     if (!w.fused && max_chunk(g, p) < kSamplePad)
         return fail(COS_EINVAL, w_ + ": a level is too wide for the streamed plan");
 

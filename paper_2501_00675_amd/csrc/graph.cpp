@@ -433,14 +433,14 @@ cos_status build_graph(int32_t L, const int64_t *widths, const int64_t *edges_pe
     if (!lookup)
         G.h16 = headroom16(G, row_ptr);
 
-    // panel plan of wide rational graphs without rows of high in-degree: each
+    // panel plan of wide graphs without rows of high in-degree: each
     // interior level's rows in two halves of about equal edge counts, each half
     // cut into panels of consecutive rows whose records and row offsets fit
     // the LDS budget, at least 32 per half (one per CU of an XCD) and a
     // multiple of 32, of about equal edge counts
     std::vector<int32_t> panels;  // (first row, end row, first edge, end edge)
     // (a source's byte offset within a tile of the level must fit 32 bits)
-    G.panel_ok = !lookup && G.max_hub_chunks == 0 && G.max_width >= kPanelMinWidth &&
+    G.panel_ok = G.max_hub_chunks == 0 && G.max_width >= kPanelMinWidth &&
                  G.max_width < (int64_t{1} << 24) && L >= 2;
     for (int32_t l = 1; l < L && G.panel_ok; ++l) {
         LevelDesc &d = G.levels[l - 1];

@@ -176,24 +176,25 @@ __global__ __launch_bounds__(kBlock) void final_partial_kernel(
 }
 
 // Final node, pass 1, with level L-1 stored tile-major by the panel plan
-// (values of type V, rational factors): as final_partial_kernel, sample s of
-// node src being prev[((s / tile) * wbuf + src) * tile + s % tile].
-template <int K, typename V>
+// (values of type V): as final_partial_kernel, sample s of node src being
+// prev[((s / tile) * wbuf + src) * tile + s % tile].
+template <int K, typename V, int KIND>
 __global__ __launch_bounds__(kBlock) void final_partial_tm_kernel(
-    const EdgeRec *__restrict__ edges, int32_t n_edges, int32_t n_chunks, const V *__restrict__ prev,
-    int64_t wbuf, int64_t ld, const double *__restrict__ x, int64_t S, int64_t xs, double *__restrict__ partial) {
+    const typename FinalPath<KIND>::Rec *__restrict__ edges, int32_t n_edges, int32_t n_chunks,
+    const V *__restrict__ prev, int64_t wbuf, int64_t ld, const double *__restrict__ x, int64_t S, int64_t xs,
+    double *__restrict__ partial) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = blockIdx.x / n_chunks;
     const int c = blockIdx.x - tile * n_chunks;
     const int64_t tbase = static_cast<int64_t>(tile) * (kWave * K);
-    LaneSamples<K> smp;
+    typename FinalPath<KIND>::template Samples<K> smp;
     smp.load(x, S, xs, tbase, lane);
     const int c_end = min((c + 1) * kFinalChunk, n_edges);
     const int e_lo = min(c * kFinalChunk + wave * kQuarter, c_end);
     const int e_hi = min(e_lo + kQuarter, c_end);
     double acc[K];
-    final_sum<K, true>(edges, e_lo, e_hi, smp, [&](const EdgeRec &r, int m) -> double {
+    final_sum<K, true>(edges, e_lo, e_hi, smp, [&](const auto &r, int m) -> double {
         const int64_t s = tbase + lane + kWave * m;
         constexpr int kTile = panel_tile(sizeof(V));
         return static_cast<double>(prev[((s / kTile) * wbuf + r.src) * kTile + s % kTile]);
@@ -368,12 +369,22 @@ hipError_t launch_level(const Graph &g, int l, cos_precision p, const void *prev
 namespace {
 
 // t32[i][s] = fl32(x[i][s]) (nearest even) for s < S, 0 for S <= s < ld.
+template <bool TILE_MAJOR>
 __global__ __launch_bounds__(kBlock) void table32_kernel(const double *__restrict__ x, int64_t xs, int64_t S,
                                                          int32_t n, float *__restrict__ t32, int64_t ld) {
+    constexpr int64_t kTile = panel_tile(sizeof(float));
     const int64_t total = static_cast<int64_t>(n) * ld;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < total;
          i += static_cast<int64_t>(gridDim.x) * kBlock) {
-        const int64_t row = i / ld, s = i - row * ld;
+        int64_t row, s;
+        if constexpr (TILE_MAJOR) {  // i = (tile * n + row) * kTile + j, sample tile * kTile + j
+            const int64_t tr = i / kTile;
+            row = tr % n;
+            s = (tr / n) * kTile + (i - tr * kTile);
+        } else {
+            row = i / ld;
+            s = i - row * ld;
+        }
         t32[i] = s < S ? static_cast<float>(x[row * xs + s]) : 0.0f;
     }
 }
@@ -381,13 +392,18 @@ __global__ __launch_bounds__(kBlock) void table32_kernel(const double *__restric
 }  // namespace
 
 hipError_t launch_table32(const double *x, int64_t xs, int64_t S, int32_t n, float *t32, int64_t ld,
-                          hipStream_t s) {
+                          hipStream_t s, bool tile_major) {
     const int64_t total = static_cast<int64_t>(n) * ld;
     if (total <= 0)
         return hipSuccess;
     TimedLaunch tl(KK_FILL, s);
     const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, 8192);
-    hipLaunchKernelGGL(table32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, x, xs, S, n, t32, ld);
+    if (tile_major)
+        hipLaunchKernelGGL(table32_kernel<true>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, x, xs, S, n,
+                           t32, ld);
+    else
+        hipLaunchKernelGGL(table32_kernel<false>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, x, xs, S,
+                           n, t32, ld);
     return hipGetLastError();
 }
 
@@ -434,22 +450,26 @@ hipError_t launch_final(const Graph &g, cos_precision p, const void *prev, int64
                         int32_t *out_exp, hipStream_t s, bool tile_major) {
     hipError_t err;
     if (tile_major) {
-        if (g.kind != FK_RATIONAL || p == COS_FP64 || prev == nullptr)
+        if (p == COS_FP64 || prev == nullptr || (g.kind == FK_LOOKUP && value_bytes(p) != 4))
             return hipErrorInvalidValue;
         const LevelDesc &d = g.levels[g.L - 1];
         const dim3 grid(static_cast<unsigned>(ld / (kWave * kKFinal) * chunks));
         const EdgeRec *e = g.d_edges + d.e_begin;
         const int32_t ne = static_cast<int32_t>(d.n_edges);
         TimedLaunch tl(KK_FINAL_PARTIAL, s);
-        if (p == COS_FP16_RESCALED)
-            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, _Float16>), grid, dim3(kBlock), 0, s, e, ne, chunks,
-                               static_cast<const _Float16 *>(prev), g.max_width, ld, x, S, xs, partial);
+        if (g.kind == FK_LOOKUP)
+            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, float, FK_LOOKUP>), grid, dim3(kBlock), 0, s,
+                               g.d_edgesL + d.e_begin, ne, chunks, static_cast<const float *>(prev), g.max_width, ld,
+                               x, S, xs, partial);
+        else if (p == COS_FP16_RESCALED)
+            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, _Float16, FK_RATIONAL>), grid, dim3(kBlock), 0, s, e,
+                               ne, chunks, static_cast<const _Float16 *>(prev), g.max_width, ld, x, S, xs, partial);
         else if (p == COS_BF16_RESCALED)
-            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, __bf16>), grid, dim3(kBlock), 0, s, e, ne, chunks,
-                               static_cast<const __bf16 *>(prev), g.max_width, ld, x, S, xs, partial);
+            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, __bf16, FK_RATIONAL>), grid, dim3(kBlock), 0, s, e,
+                               ne, chunks, static_cast<const __bf16 *>(prev), g.max_width, ld, x, S, xs, partial);
         else
-            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, float>), grid, dim3(kBlock), 0, s, e, ne, chunks,
-                               static_cast<const float *>(prev), g.max_width, ld, x, S, xs, partial);
+            hipLaunchKernelGGL((final_partial_tm_kernel<kKFinal, float, FK_RATIONAL>), grid, dim3(kBlock), 0, s, e,
+                               ne, chunks, static_cast<const float *>(prev), g.max_width, ld, x, S, xs, partial);
         err = hipGetLastError();
     } else {
         err = g.kind == FK_LOOKUP ? launch_final_partial<FK_LOOKUP>(g, p, prev, ld, x, S, xs, partial, chunks, s)

@@ -45,6 +45,15 @@ struct PanelRec {
     uint32_t soff;
 };
 static_assert(sizeof(PanelRec) == 24, "PanelRec layout");
+// The same for lookup factors: the binary32 constant and the byte offset of
+// the edge's table slot within a tile of the tile-major binary32 tables.
+struct PanelRecL {
+    float coef;
+    uint32_t toff;
+    uint32_t unused[3];
+    uint32_t soff;
+};
+static_assert(sizeof(PanelRecL) == sizeof(PanelRec), "PanelRecL layout");
 
 // A sample of the current block of tiles in LDS: its coordinates rounded to
 // binary32 and the exponent shift of the previous level (0 without rescale).
@@ -107,13 +116,19 @@ struct PanelIO<__bf16> : PanelIO16<__bf16> {};
 // V: storage type of the level values (binary32, or binary16 / bfloat16 under
 // RESCALE).  h_next: the next level's headroom exponent (binary16), by which
 // this level's largest |value| is raised before it is folded into cur_max.
-template <bool FROM_ROOT, bool RESCALE, typename V>
+// LOOKUP: lookup factors coef32 * T_s[slot] at binary32 storage, the tables
+// t32 tile-major ([tile][slot][kTile], n_tab lines per tile; a tile's tables
+// stay in L2), a row's entries gathered as the row starts.
+template <bool FROM_ROOT, bool RESCALE, typename V, bool LOOKUP>
 __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
     const int32_t *__restrict__ panels, int32_t n_half0, int32_t n_panels, const EdgeRec32 *__restrict__ edges,
+    const EdgeRecL *__restrict__ edgesL, const float *__restrict__ t32, int32_t n_tab,
     const int32_t *__restrict__ row_ptr, const V *__restrict__ prev, V *__restrict__ cur, int64_t wbuf,
     int64_t n_tiles, const double *__restrict__ x, int64_t S, int64_t xs, const uint32_t *__restrict__ prev_max,
     uint32_t *__restrict__ cur_max, int32_t h_next) {
+    static_assert(!LOOKUP || std::is_same_v<V, float>, "lookup factors on the panel plan at binary32 storage");
     using IO = PanelIO<V>;
+    using Rec = std::conditional_t<LOOKUP, PanelRecL, PanelRec>;
     constexpr int kTile = panel_tile(sizeof(V));       // samples per tile
     constexpr int kBlockTiles = kPanelBlockSamples / kTile;
     static_assert(kBlockTiles * kTile == kPanelBlockSamples, "whole tiles per sample block");
@@ -149,17 +164,27 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
         const int nr = re - rb, ne = ee - eb;
         // LDS: records from address 0 (a row's records are then reached by instruction offsets), kPanelPadRecs
         // zeroed ones (source 0), the row offsets, then the sample block at the next 16-byte boundary
-        PanelRec *rec = reinterpret_cast<PanelRec *>(lds);
-        const size_t rec_bytes = static_cast<size_t>(ne + kPanelPadRecs) * sizeof(PanelRec);
+        Rec *rec = reinterpret_cast<Rec *>(lds);
+        const size_t rec_bytes = static_cast<size_t>(ne + kPanelPadRecs) * sizeof(Rec);
         int32_t *off = reinterpret_cast<int32_t *>(lds + rec_bytes);
         PanelSample *smp = reinterpret_cast<PanelSample *>(lds + ((rec_bytes + (nr + 1) * 4 + 15) & ~size_t(15)));
         __syncthreads();  // the previous panel's records are no longer read
         for (int i = tid; i < ne + kPanelPadRecs; i += kPanelThreads) {
-            if (i < ne) {
-                const EdgeRec32 &e = edges[eb + i];
-                rec[i] = PanelRec{e.a, e.b, e.k0, e.k1, e.k2, static_cast<uint32_t>(e.src) * kPanelLine};
+            if constexpr (LOOKUP) {
+                if (i < ne) {
+                    const EdgeRecL &e = edgesL[eb + i];
+                    rec[i] = PanelRecL{e.coef32, static_cast<uint32_t>(e.slot) * kPanelLine, {0u, 0u, 0u},
+                                       static_cast<uint32_t>(e.src) * kPanelLine};
+                } else {
+                    rec[i] = PanelRecL{0.0f, 0u, {0u, 0u, 0u}, 0u};
+                }
             } else {
-                rec[i] = PanelRec{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
+                if (i < ne) {
+                    const EdgeRec32 &e = edges[eb + i];
+                    rec[i] = PanelRec{e.a, e.b, e.k0, e.k1, e.k2, static_cast<uint32_t>(e.src) * kPanelLine};
+                } else {
+                    rec[i] = PanelRec{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
+                }
             }
         }
         for (int i = tid; i <= nr; i += kPanelThreads)
@@ -178,8 +203,17 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                 return *reinterpret_cast<const Raw *>(reinterpret_cast<const char *>(prev) + t * wbuf * kPanelLine +
                                                       (rec[k].soff + qoff));
         };
+        // table entries of LDS edge k for the lane's samples of tile t (lookup factors)
+        auto tgather = [&](int64_t t, int k) -> float4 {
+            if constexpr (LOOKUP)
+                return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(t32) +
+                                                         t * n_tab * kPanelLine + (rec[k].toff + qoff));
+            else
+                return float4{};
+        };
         // the first kGroup gathers of row i for tile t, issued unconditionally: records past the row are
-        // later records or the zeroed padding, whose sources are rows of the previous level (never summed)
+        // later records or the zeroed padding, whose sources are rows of the previous level and whose slots
+        // are slots of the tables (never summed)
         auto issue = [&](int64_t t, int i, Raw (&v)[kGroup]) {
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
@@ -196,7 +230,7 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                 for (int i = tid; i < kPanelBlockSamples; i += kPanelThreads) {
                     const int64_t s = t * kTile + i;
                     PanelSample v{0.0f, 0.0f, 0.0f, 0};
-                    if (s < S)
+                    if (!LOOKUP && s < S)
                         v = PanelSample{static_cast<float>(x[s]), static_cast<float>(x[xs + s]),
                                         static_cast<float>(x[2 * xs + s]), 0};
                     if (RESCALE && prev_max && s < n_tiles * kTile)
@@ -226,27 +260,41 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
                     issue(t, i + 1, buf[(i + 1) & 1]);
                 else  // the next tile's first row (on the last tile, an unused repeat of this tile's)
                     issue(min(t + 1, t1 - 1), 0, buf[0]);
+                const int kbi = kbf(i), kei = kef(i);
+                float4 tbuf[LOOKUP ? kGroup : 1];  // this row's table entries (lookup factors)
+                if constexpr (LOOKUP)
+#pragma unroll
+                    for (int u = 0; u < kGroup; ++u)
+                        tbuf[u] = tgather(t, kbi + u);
                 float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
                 // edge k added to the sums when `use` (the group's records past the row are formed and
                 // dropped)
-                auto add = [&](int k, const Raw &v, bool use) {
-                    const PanelRec g = rec[k];
-                    const EdgeRec32 e{g.a, g.b, g.k0, g.k1, g.k2, 0, 0, 0};
+                auto add = [&](int k, const Raw &v, const float4 &tv, bool use) {
+                    const Rec g = rec[k];
                     float vv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
                     if constexpr (!FROM_ROOT)
                         IO::widen(v, vv);
+                    if constexpr (LOOKUP) {
+                        const float tt[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const float f = __builtin_fmaf(edge_factor32(e, x0[j], x1[j], x2[j]), vv[j], acc[j]);
-                        acc[j] = use ? f : acc[j];
+                        for (int j = 0; j < 4; ++j) {
+                            const float f = __builtin_fmaf(g.coef * tt[j], vv[j], acc[j]);
+                            acc[j] = use ? f : acc[j];
+                        }
+                    } else {
+                        const EdgeRec32 e{g.a, g.b, g.k0, g.k1, g.k2, 0, 0, 0};
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float f = __builtin_fmaf(edge_factor32(e, x0[j], x1[j], x2[j]), vv[j], acc[j]);
+                            acc[j] = use ? f : acc[j];
+                        }
                     }
                 };
-                const int kbi = kbf(i), kei = kef(i);
 #pragma unroll
                 for (int u = 0; u < kGroup; ++u)
-                    add(kbi + u, buf[i & 1][u], kbi + u < kei);
+                    add(kbi + u, buf[i & 1][u], tbuf[LOOKUP ? u : 0], kbi + u < kei);
                 for (int k = kbi + kGroup; k < kei; ++k)  // rows of more than kGroup edges
-                    add(k, gather(t, k), true);
+                    add(k, gather(t, k), tgather(t, k), true);
                 const int r = rsub + i * kRowsPerStep;
                 if (r < nr) {
                     float z[4];
@@ -291,13 +339,13 @@ __global__ __launch_bounds__(kPanelThreads) void level_panel_kernel(
 }
 
 // Allow a panel's dynamic LDS (beyond the default limit) once per instantiation.
-template <bool FROM_ROOT, bool RESCALE, typename V>
+template <bool FROM_ROOT, bool RESCALE, typename V, bool LOOKUP>
 hipError_t panel_launch(dim3 grid, size_t lds, hipStream_t s, const int32_t *pan, int32_t n0, int32_t n,
-                        const EdgeRec32 *edges, const int32_t *rp, const void *prev, void *cur, int64_t wbuf,
+                        const Graph &g, const float *t32, const int32_t *rp, const void *prev, void *cur,
                         int64_t ld, const double *x, int64_t S, int64_t xs, const uint32_t *prev_max,
                         uint32_t *cur_max, int32_t h_next) {
     static std::atomic<bool> attr_set{false};
-    auto kern = level_panel_kernel<FROM_ROOT, RESCALE, V>;
+    auto kern = level_panel_kernel<FROM_ROOT, RESCALE, V, LOOKUP>;
     if (!attr_set.load(std::memory_order_acquire)) {
         const hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -307,34 +355,38 @@ hipError_t panel_launch(dim3 grid, size_t lds, hipStream_t s, const int32_t *pan
         attr_set.store(true, std::memory_order_release);  // setting it twice is harmless
     }
     const int64_t n_tiles = ld / panel_tile(sizeof(V));
-    hipLaunchKernelGGL(kern, grid, dim3(kPanelThreads), lds, s, pan, n0, n, edges, rp,
-                       static_cast<const V *>(prev), static_cast<V *>(cur), wbuf, n_tiles, x, S, xs, prev_max,
-                       cur_max, h_next);
+    hipLaunchKernelGGL(kern, grid, dim3(kPanelThreads), lds, s, pan, n0, n, g.d_edges32, g.d_edgesL, t32,
+                       g.n_slots, rp, static_cast<const V *>(prev), static_cast<V *>(cur), g.max_width, n_tiles, x,
+                       S, xs, prev_max, cur_max, h_next);
     return hipGetLastError();
 }
 
-template <bool RESCALE, typename V>
+template <bool RESCALE, typename V, bool LOOKUP = false>
 hipError_t panel_launch_level(bool root, dim3 grid, size_t lds, hipStream_t s, const int32_t *pan, int32_t n0,
-                              int32_t n, const EdgeRec32 *edges, const int32_t *rp, const void *prev, void *cur,
-                              int64_t wbuf, int64_t ld, const double *x, int64_t S, int64_t xs,
+                              int32_t n, const Graph &g, const float *t32, const int32_t *rp, const void *prev,
+                              void *cur, int64_t ld, const double *x, int64_t S, int64_t xs,
                               const uint32_t *prev_max, uint32_t *cur_max, int32_t h_next) {
-    return root ? panel_launch<true, RESCALE, V>(grid, lds, s, pan, n0, n, edges, rp, prev, cur, wbuf, ld, x, S, xs,
-                                                 prev_max, cur_max, h_next)
-                : panel_launch<false, RESCALE, V>(grid, lds, s, pan, n0, n, edges, rp, prev, cur, wbuf, ld, x, S, xs,
-                                                  prev_max, cur_max, h_next);
+    return root ? panel_launch<true, RESCALE, V, LOOKUP>(grid, lds, s, pan, n0, n, g, t32, rp, prev, cur, ld, x, S,
+                                                         xs, prev_max, cur_max, h_next)
+                : panel_launch<false, RESCALE, V, LOOKUP>(grid, lds, s, pan, n0, n, g, t32, rp, prev, cur, ld, x, S,
+                                                          xs, prev_max, cur_max, h_next);
 }
 
 }  // namespace
 
 bool panel_fits(const Graph &g, cos_precision p) {
+    if (g.kind == FK_LOOKUP)
+        return g.panel_ok && (p == COS_FP32 || p == COS_FP32_RESCALED);
     return g.panel_ok && (p == COS_FP32 || p == COS_FP32_RESCALED || p == COS_FP16_RESCALED || p == COS_BF16_RESCALED);
 }
 
 hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const void *prev, void *cur, int64_t ld,
                               const double *x, int64_t S, int64_t xs, const uint32_t *prev_max, uint32_t *cur_max,
-                              int32_t h_next, hipStream_t s) {
+                              int32_t h_next, const float *t32, hipStream_t s) {
     const LevelDesc &d = g.levels[l - 1];
-    if (!panel_fits(g, p) || ld % (4 * panel_tile(value_bytes(p))) != 0 || d.panel_lds > kPanelLdsBytes)
+    const bool lookup = g.kind == FK_LOOKUP;
+    if (!panel_fits(g, p) || ld % (4 * panel_tile(value_bytes(p))) != 0 || d.panel_lds > kPanelLdsBytes ||
+        (lookup && t32 == nullptr))
         return hipErrorInvalidValue;
     // one workgroup per CU: 32 per XCD
     const dim3 grid(kXcds * 32);
@@ -344,20 +396,22 @@ hipError_t launch_level_panel(const Graph &g, int l, cos_precision p, const void
     const int32_t *rp = g.d_row_ptr + d.rp_begin;
     const bool root = prev == nullptr;
     TimedLaunch tl(KK_LEVEL, s);
-    const EdgeRec32 *e = g.d_edges32;
-    const int64_t wb = g.max_width;
     switch (p) {
     case COS_FP32_RESCALED:
-        return panel_launch_level<true, float>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S, xs,
-                                               prev_max, cur_max, h_next);
+        return lookup ? panel_launch_level<true, float, true>(root, grid, lds, s, pan, n0, n, g, t32, rp, prev, cur,
+                                                              ld, x, S, xs, prev_max, cur_max, h_next)
+                      : panel_launch_level<true, float>(root, grid, lds, s, pan, n0, n, g, t32, rp, prev, cur, ld, x,
+                                                        S, xs, prev_max, cur_max, h_next);
     case COS_FP32:
-        return panel_launch_level<false, float>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S, xs,
-                                                nullptr, nullptr, 0);
+        return lookup ? panel_launch_level<false, float, true>(root, grid, lds, s, pan, n0, n, g, t32, rp, prev, cur,
+                                                               ld, x, S, xs, nullptr, nullptr, 0)
+                      : panel_launch_level<false, float>(root, grid, lds, s, pan, n0, n, g, t32, rp, prev, cur, ld,
+                                                         x, S, xs, nullptr, nullptr, 0);
     case COS_FP16_RESCALED:
-        return panel_launch_level<true, _Float16>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S,
+        return panel_launch_level<true, _Float16>(root, grid, lds, s, pan, n0, n, g, t32, rp, prev, cur, ld, x, S,
                                                   xs, prev_max, cur_max, h_next);
     case COS_BF16_RESCALED:
-        return panel_launch_level<true, __bf16>(root, grid, lds, s, pan, n0, n, e, rp, prev, cur, wb, ld, x, S, xs,
+        return panel_launch_level<true, __bf16>(root, grid, lds, s, pan, n0, n, g, t32, rp, prev, cur, ld, x, S, xs,
                                                 prev_max, cur_max, h_next);
     default:
         return hipErrorInvalidValue;

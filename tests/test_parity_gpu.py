@@ -596,6 +596,27 @@ def test_panel_plan_16bit_bit_identical_to_streamed(P, precision, S):
         assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
 
 
+@pytest.mark.parametrize("precision", ["fp32r", "fp32"])
+@pytest.mark.parametrize("S", [70, 1000])
+def test_panel_plan_lookup_factors_bit_identical_to_streamed(P, precision, S):
+    # lookup factors (w = coef32 * T_s[slot] from the binary32 tables, tile-major on the panel plan): the
+    # streamed plan's bits; binary32 storage only (16-bit storage of lookup graphs stays streamed)
+    g, T = make_config("precision", S=S, width=8192, L=5, degree=6, seed=23, factor="lookup")
+    G = graph(P, g)
+    mask = G.info()["panel_mask"]
+    assert (mask >> P.PRECISIONS[precision]) & 1 and not (mask >> P.PRECISIONS["bf16r"]) & 1
+    say(f"lookup panel vs streamed {precision} S={S}")
+    yp = gpu_eval(G.set_path("panel"), T, precision)
+    ys = gpu_eval(G.set_path("streamed"), T, precision)
+    assert np.array_equal(yp.view(np.uint64), ys.view(np.uint64))
+    small = torch.empty(G.workspace_bytes(256, precision), dtype=torch.uint8, device="cuda:0")
+    yc = gpu_eval(G.set_path("panel"), T, precision, workspace=small)  # sweeps of 256 samples
+    assert np.array_equal(yc.view(np.uint64), ys.view(np.uint64))
+    idx = sample_subset(S, 48, seed=3)
+    V, Q = oracle_ref(g, T, idx)
+    assert_parity(yp[idx], V, Q, precision, "lookup panel")
+
+
 def test_panel_plan_uneven_rows_and_chunked_sweeps(P):
     # irregular in-degrees (1..13), rows without in-edges, a ragged sample count and a workspace that
     # forces sweeps of 512 samples: the panel plan keeps the streamed plan's bits
